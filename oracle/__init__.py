@@ -1,0 +1,243 @@
+"""CPU oracle for the phi-combination method -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, single-threaded IEEE-double C (``phicomb_oracle.c``) following
+Algorithms 1-3 of Al-Mohy, "Computing Linear Combinations of phi-Function
+Actions for Exponential Integrators" (arXiv 2509.26475), step by step.
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package; the HIP library never does, and the
+two share no code.
+
+Blocks cross this wrapper row-major ([n][p+1] for V, [n][r] for W) to match
+the library's layout; the C code works column-major internally, so the
+wrapper transposes (a layout change only).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "phicomb_oracle.c")
+_LIB = os.path.join(_HERE, "libphicomb_oracle.so")
+_lib = None
+
+BRENT_REL = 1.4901161193847656e-08   # sqrt(2^-52)
+BRENT_ABS = 1e-6                     # absolute tolerance in z = -xi/s0
+BRENT_MAXIT = 100
+KCAP = 150                           # Taylor-term cap per loop (sigma = k! < 2^1024)
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -4: "ENOCONV", -5: "EOVERFLOW"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status):
+        super().__init__(f"oracle status {status} ({STATUS.get(status, '?')})")
+        self.status = status
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11",
+               "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Op(C.Structure):
+    _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("pad", C.c_int32),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("dense", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("shift", C.c_double), ("s0", C.c_double), ("zstar", C.c_double),
+                ("fstar", C.c_double), ("s", C.c_double), ("m", C.c_int32),
+                ("r_acc", C.c_int32), ("n_feval", C.c_int32), ("status", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("s_int", C.c_int32), ("terms_S", C.c_int32), ("terms_rec", C.c_int32),
+                ("max_terms_step", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+_FUN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_void_p)
+
+
+def _configure(lib):
+    P = C.c_void_p
+    lib.orc_params.argtypes = [P, C.c_double, C.c_int, P, C.c_double, C.c_double,
+                               C.c_int, P, P, P]
+    lib.orc_params.restype = C.c_int
+    lib.orc_solve.argtypes = [P, C.c_int, C.c_int, P, P, P, C.c_int, P, C.c_double,
+                              C.c_double, C.c_double, C.c_int, P, P]
+    lib.orc_solve.restype = C.c_int
+    lib.orc_solve_single.argtypes = [P, C.c_int, C.c_double, C.c_double, P, C.c_double,
+                                     C.c_double, C.c_double, C.c_int, P, P]
+    lib.orc_solve_single.restype = C.c_int
+    lib.orc_brent_min.argtypes = [_FUN, P, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_int, P, P]
+    lib.orc_brent_min.restype = C.c_double
+    lib.orc_apply.argtypes = [P, P, P]
+    lib.orc_apply.restype = None
+    lib.orc_binom.argtypes = [C.c_int, C.c_int]
+    lib.orc_binom.restype = C.c_double
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _lib = _configure(C.CDLL(_LIB))
+    return _lib
+
+
+class using_library:
+    """Context manager: route every call through another build of the
+    oracle source (the mutation tests compile planted-mistake copies)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _load()
+        _lib = _configure(C.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Operator:
+    """Keeps the arrays alive and exposes the C descriptor."""
+
+    def __init__(self, op):
+        kind = getattr(op, "kind", None)
+        self.keep = []
+        s = _Op()
+        if kind == "dense":
+            A = np.ascontiguousarray(op.A, dtype=np.float64)
+            self.keep.append(A)
+            s.n, s.kind, s.dense = A.shape[0], 1, A.ctypes.data
+        else:
+            rp, ci, va = op.csr()
+            rp = np.ascontiguousarray(rp, dtype=np.int32)
+            ci = np.ascontiguousarray(ci, dtype=np.int32)
+            va = np.ascontiguousarray(va, dtype=np.float64)
+            self.keep += [rp, ci, va]
+            s.n, s.kind = rp.shape[0] - 1, 0
+            s.rowptr, s.col, s.val = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+        self.s = s
+        self.n = int(s.n)
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _as_op(op):
+    return op if isinstance(op, Operator) else Operator(op)
+
+
+def apply(op, x: np.ndarray) -> np.ndarray:
+    o = _as_op(op)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    _load().orc_apply(o.ref, _ptr(x), _ptr(y))
+    return y
+
+
+def binom(m: int, k: int) -> float:
+    return float(_load().orc_binom(m, k))
+
+
+def params(op, tol: float, v: np.ndarray, m: int = 61, brent_rel: float = BRENT_REL,
+           brent_abs: float = BRENT_ABS, brent_maxit: int = BRENT_MAXIT,
+           want_basis: bool = False) -> dict:
+    """Algorithm 1.  Returns a dict with shift, s0, zstar, fstar, s, m,
+    r_acc, n_feval, L (log-norms of the accepted powers) and optionally
+    the normalised basis [m+1][n]."""
+    o = _as_op(op)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = _Params()
+    L = np.zeros(m + 1)
+    basis = np.zeros((m + 1, o.n)) if want_basis else None
+    st = _load().orc_params(o.ref, tol, m, _ptr(v), brent_rel, brent_abs, brent_maxit,
+                            C.byref(out), _ptr(L), _ptr(basis) if want_basis else None)
+    if st != 0:
+        raise OracleError(st)
+    res = {f: getattr(out, f) for f, _ in _Params._fields_}
+    res["L"] = L
+    res["tol"] = tol
+    if want_basis:
+        res["basis"] = basis
+    return res
+
+
+def solve(op, p: int, r: int, t, beta, V: np.ndarray, tol: float, shift: float, s: float,
+          form: str = "beta", alpha=None, kcap: int = KCAP):
+    """Algorithm 3.  V: [n][p+1] row-major.  Returns (W [n][r], stats)."""
+    o = _as_op(op)
+    n = o.n
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    Vc = np.ascontiguousarray(np.asarray(V, dtype=np.float64).T)   # column-major
+    assert Vc.shape == (p + 1, n)
+    beta_a = np.ascontiguousarray(beta, dtype=np.float64) if beta is not None else None
+    alpha_a = np.ascontiguousarray(alpha, dtype=np.float64) if alpha is not None else None
+    Wc = np.zeros((r, n))
+    stt = _Stats()
+    st = _load().orc_solve(o.ref, p, r, _ptr(t), _ptr(beta_a) if beta_a is not None else None,
+                           _ptr(alpha_a) if alpha_a is not None else None,
+                           0 if form == "beta" else 1, _ptr(Vc), tol, shift, s, kcap,
+                           _ptr(Wc), C.byref(stt))
+    if st != 0:
+        raise OracleError(st)
+    stats = {f: getattr(stt, f) for f, _ in _Stats._fields_ if f != "pad"}
+    return np.ascontiguousarray(Wc.T), stats
+
+
+def solve_single(op, p: int, t: float, alpha: float, V: np.ndarray, tol: float,
+                 shift: float, s: float, kcap: int = KCAP):
+    """Algorithm 2.  Returns (w [n], stats)."""
+    o = _as_op(op)
+    Vc = np.ascontiguousarray(np.asarray(V, dtype=np.float64).T)
+    w = np.zeros(o.n)
+    stt = _Stats()
+    st = _load().orc_solve_single(o.ref, p, float(t), float(alpha), _ptr(Vc), tol, shift, s,
+                                  kcap, _ptr(w), C.byref(stt))
+    if st != 0:
+        raise OracleError(st)
+    return w, {f: getattr(stt, f) for f, _ in _Stats._fields_ if f != "pad"}
+
+
+def brent_min(f, a: float, b: float, rel: float = BRENT_REL, abs_tol: float = BRENT_ABS,
+              maxit: int = BRENT_MAXIT):
+    cb = _FUN(lambda x, ctx: float(f(x)))
+    fmin = C.c_double()
+    nfev = C.c_int()
+    x = _load().orc_brent_min(cb, None, a, b, rel, abs_tol, maxit, C.byref(fmin), C.byref(nfev))
+    return x, fmin.value, nfev.value
+
+
+def full(problem, m: int = 61, form: str = "beta", kcap: int = KCAP, prm: Optional[dict] = None):
+    """Algorithm 1 then Algorithm 3 on a workloads.Problem."""
+    o = Operator(problem.op)
+    if prm is None:
+        prm = params(o, problem.tol, problem.v, m=m)
+    W, st = solve(o, problem.p, problem.r, problem.t, problem.beta, problem.V, problem.tol,
+                  prm["shift"], prm["s"], form=form, alpha=problem.alpha, kcap=kcap)
+    return W, st, prm

@@ -1,0 +1,172 @@
+"""Exact references used to pin the oracle (test helpers; no oracle code).
+
+Each helper computes w_i = sum_j beta_ij phi_j(t_i A) v_j (paper, Sec. 1,
+(phi.comb)) by a route that is independent of the method:
+
+* ``phi_mp`` / ``phi_ld``: the scalar phi-functions from their definition
+  (Sec. 1, (def.phik)): series sum_k z^k/(k+j)! near 0, otherwise
+  phi_0 = e^z and phi_{j+1}(z) = (phi_j(z) - 1/j!)/z.
+* ``augmented_mp``: the exact augmented-matrix form used by the paper for
+  its reference solutions (Sec. 5, first experiment; Theorem 1's proof):
+  w = [I 0] exp([[tA, [w_p .. w_1]], [0, J_p(0)]]) [w_0; e_p] with
+  w_j = beta_j v_j, evaluated by mpmath at high precision.
+* ``dst_laplacian``: the textbook eigen-decomposition of a Dirichlet
+  Laplacian stencil (orthonormal DST-I), scalar phi at every eigenvalue.
+* ``expm_multiply_aug``: scipy's expm_multiply on the sparse augmented
+  matrix (Al-Mohy & Higham 2011, the paper's [alhi11]).
+"""
+from __future__ import annotations
+
+import math
+
+import mpmath
+import numpy as np
+import scipy.fft
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def phi_mp(j: int, z, dps: int = 50):
+    """phi_j(z) at ``dps`` digits (definition (def.phik))."""
+    with mpmath.workdps(dps):
+        z = mpmath.mpf(z) if not isinstance(z, mpmath.mpc) else z
+        if abs(z) < 2:
+            acc = mpmath.mpf(0)
+            term = mpmath.mpf(1) / mpmath.factorial(j)
+            k = 0
+            while True:
+                acc += term
+                k += 1
+                term = term * z / (k + j)
+                if abs(term) < mpmath.mpf(10) ** (-dps - 5) * (abs(acc) + 1):
+                    break
+            return acc
+        s = mpmath.exp(z)
+        for k in range(j):
+            s -= z ** k / mpmath.factorial(k)
+        return s / z ** j
+
+
+def phi_ld(j: int, z: np.ndarray) -> np.ndarray:
+    """Vectorised phi_j in extended (80-bit) precision, returned as float64.
+    Series for |z| < 8, recurrence from e^z otherwise (stable there since
+    every step divides by |z| > j)."""
+    z = np.asarray(z, dtype=np.longdouble)
+    out = np.empty(z.shape, dtype=np.longdouble)
+    small = np.abs(z) < 8
+    if small.any():
+        zs = z[small]
+        acc = np.zeros_like(zs)
+        term = np.full_like(zs, 1) / np.longdouble(math.factorial(j))
+        for k in range(1, 90):
+            acc += term
+            term = term * zs / (k + j)
+        out[small] = acc
+    big = ~small
+    if big.any():
+        zb = z[big]
+        ph = np.exp(zb)
+        fact = np.longdouble(1)
+        for k in range(j):
+            ph = (ph - 1 / fact) / zb
+            fact *= (k + 1)
+        out[big] = ph
+    return out.astype(np.float64)
+
+
+def augmented_mp(A: np.ndarray, t_i: float, beta_i: np.ndarray, V: np.ndarray,
+                 dps: int = 40) -> np.ndarray:
+    """Exact w_i from the augmented exponential (V: [n][p+1])."""
+    n, P1 = V.shape
+    p = P1 - 1
+    with mpmath.workdps(dps):
+        M = mpmath.zeros(n + p, n + p)
+        for a in range(n):
+            for b in range(n):
+                M[a, b] = mpmath.mpf(t_i) * mpmath.mpf(A[a, b])
+        # columns n..n+p-1 of the (1,2) block: [w_p, w_{p-1}, ..., w_1]
+        for c in range(p):
+            j = p - c
+            for a in range(n):
+                M[a, n + c] = mpmath.mpf(beta_i[j]) * mpmath.mpf(V[a, j])
+        for c in range(p - 1):
+            M[n + c, n + c + 1] = 1
+        E = mpmath.expm(M)
+        rhs = mpmath.zeros(n + p, 1)
+        for a in range(n):
+            rhs[a] = mpmath.mpf(beta_i[0]) * mpmath.mpf(V[a, 0])
+        if p > 0:
+            rhs[n + p - 1] = 1
+        w = E * rhs
+        return np.array([float(w[a]) for a in range(n)])
+
+
+def exact_dense_mp(A, t, beta, V, dps=40):
+    return np.stack([augmented_mp(A, t[i], beta[i], V, dps) for i in range(len(t))], axis=1)
+
+
+def _lap_eigs_1d(m: int, c_off: float) -> np.ndarray:
+    k = np.arange(1, m + 1)
+    return c_off * (2.0 * np.cos(k * np.pi / (m + 1)) - 2.0)
+
+
+def dst_laplacian(stencil, t, beta, V) -> np.ndarray:
+    """Exact W for a symmetric constant-coefficient Dirichlet Laplacian
+    stencil (centre = -sum of the off-diagonal coefficients, equal +/- pair
+    in every direction, no superdiagonal perturbation)."""
+    nx, ny, nz = stencil.grid
+    c = np.asarray(stencil.coef)
+    assert stencil.superdiag == 0.0
+    assert c[1] == c[2] and c[3] == c[4] and c[5] == c[6]
+    assert abs(c[0] + 2 * (c[1] + c[3] + c[5])) <= 1e-12 * abs(c[0])
+    shape = (nz, ny, nx)
+    lam = (_lap_eigs_1d(nz, c[5])[:, None, None] + _lap_eigs_1d(ny, c[3])[None, :, None]
+           + _lap_eigs_1d(nx, c[1])[None, None, :])
+    axes = (0, 1, 2) if nz > 1 else (1, 2)
+    P1 = V.shape[1]
+    coeffs = [scipy.fft.dstn(V[:, j].reshape(shape), type=1, norm="ortho", axes=axes)
+              for j in range(P1)]
+    W = np.empty((V.shape[0], len(t)))
+    for i, ti in enumerate(t):
+        acc = np.zeros(shape)
+        for j in range(P1):
+            acc += beta[i][j] * phi_ld(j, ti * lam) * coeffs[j]
+        W[:, i] = scipy.fft.idstn(acc, type=1, norm="ortho", axes=axes).ravel()
+    return W
+
+
+def expm_multiply_aug(csr, t, beta, V) -> np.ndarray:
+    """Exact-to-~1e-14 W via scipy expm_multiply on the augmented sparse
+    matrix, one abscissa at a time.  csr = (rowptr, col, val)."""
+    rp, ci, va = csr
+    n = len(rp) - 1
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    P1 = V.shape[1]
+    p = P1 - 1
+    W = np.empty((n, len(t)))
+    for i, ti in enumerate(t):
+        blocks_top = [ti * A]
+        if p > 0:
+            Wb = np.stack([beta[i][p - c] * V[:, p - c] for c in range(p)], axis=1)
+            blocks_top.append(sp.csr_matrix(Wb))
+            Jp = sp.diags([np.ones(p - 1)], [1], shape=(p, p)) if p > 1 else sp.csr_matrix((1, 1))
+            M = sp.bmat([blocks_top, [None, Jp]], format="csr")
+        else:
+            M = (ti * A).tocsr()
+        rhs = np.zeros(n + p)
+        rhs[:n] = beta[i][0] * V[:, 0]
+        if p > 0:
+            rhs[n + p - 1] = 1.0
+        W[:, i] = spla.expm_multiply(M, rhs)[:n]
+    return W
+
+
+def rel2(a, b) -> float:
+    """Relative 2-norm error ||a-b||/||b|| (Frobenius over all columns)."""
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def rel2_cols(a, b) -> np.ndarray:
+    a = np.asarray(a).reshape(b.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
