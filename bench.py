@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Throughput of the phi-combination hot path on one MI355X.
+
+One step = one pass of the whole path over one synthetic problem:
+parameter selection (Algorithm 1: power basis, objective, Brent) followed
+by the block solve (Algorithm 3) for r abscissae, with the operator and
+the vectors already resident in HBM.
+
+Workload (default): 2-D upwind convection-diffusion on a 512 x 512 grid
+(n = 262144) stored as CSR, velocity (50, 50), p = 3, r = 3,
+t_i = c_i * 1e-4 with c = (1/2, 1/3, 1), beta_ij = c_i^j, v_j ~ N(0,1)
+normalised, tol = 1e-12, FP64.
+
+Prints one JSON line.  ``roofline`` describes the solve kernel (the
+dominant kernel): algorithmic bytes per launch / its average duration
+measured with HIP events on the launch stream; ``cpu_baseline`` times the
+CPU oracle on one full step of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "phi-comb solves/s + block-SpMM HBM GB/s at tol; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("internal.h", "solve.hip"):
+        with open(os.path.join(ROOT, "paper_2509_26475_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only
+    if they were taken on the current kernel source."""
+    path = os.path.join(PROFILE_DIR, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d.get(f"{kernel}|{workload}")
+        if not e or e.get("source_hash") != kernel_source_hash():
+            return None
+        return float(e["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(problem) -> dict:
+    import oracle
+    t0 = time.perf_counter()
+    W, st, prm = oracle.full(problem)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "one full step (Algorithm 1 + Algorithm 3) of the same workload, "
+                      f"single-threaded C, {dt:.2f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kind", choices=["csr", "stencil"], default="csr")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU layout is described in the design notes, not built)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2509_26475_amd as pc
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    pr = wl.config2(as_csr=(args.kind == "csr"))
+    op = pc.Operator(pr.op)
+    V = torch.from_numpy(pr.V).cuda()
+    W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
+
+    def step():
+        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
+        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
+        return prm, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t_par = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
+        b = time.perf_counter()
+        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
+        t_par += b - a
+        stats.append(st.as_dict())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps / dt
+    ms_kernel = float(np.mean([s["ms"] for s in stats]))
+    bytes_launch = float(np.mean([s["bytes_alg"] for s in stats]))
+    achieved = bytes_launch / (ms_kernel * 1e-3) / 1e9
+    kernel_name = f"solve_kernel<{args.kind},r={pr.r}>"
+    workload = f"convdiff2d_512_{args.kind}_p3_r3_tol1e-12"
+    traffic = measured_traffic(kernel_name, workload)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": pr.n, "p": pr.p, "r": pr.r,
+                   "operator": f"{args.kind} 5-point upwind convection-diffusion 512x512",
+                   "tol": pr.tol, "step": "Algorithm 1 + Algorithm 3"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": kernel_name,
+                     "bytes_per_launch": bytes_launch, "ms_per_launch": ms_kernel},
+        "solve_only_per_s": 1e3 / ms_kernel,
+        "params_ms": 1e3 * t_par / args.steps,
+        "s_int": stats[-1]["s_int"], "terms_S": stats[-1]["terms_S"],
+        "terms_rec": stats[-1]["terms_rec"],
+        "shift": prm.shift, "s": prm.s,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(pr)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+    op.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

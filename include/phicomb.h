@@ -1,0 +1,180 @@
+/*
+ * phicomb.h -- C ABI of the MI355X (gfx950) library for linear combinations
+ * of phi-function actions,
+ *
+ *     w_i = sum_{j=0..p} beta_ij phi_j(t_i A) v_j,   i = 1..r,
+ *
+ * by the block truncated-Taylor scaling-and-recovering method of
+ * A. H. Al-Mohy, "Computing Linear Combinations of phi-Function Actions for
+ * Exponential Integrators" (arXiv 2509.26475).  The paper's problem statement
+ * is Sec. 1, eq. (phi.comb), with beta_ij = alpha_i^j; phi_j is defined in
+ * eq. (def.phik).  Any weight table beta is accepted (Corollary of Theorem 1:
+ * the weights are folded into the columns of V).
+ *
+ * Conventions
+ *  - Every function returns an int status: PHICOMB_OK (0), PHICOMB_PENDING
+ *    (1, phicomb_poll only) or a negative error.  No exception crosses the
+ *    ABI; phicomb_strerror() names a status.
+ *  - "host" pointers are ordinary CPU memory, read during the call only.
+ *    "device" pointers are HIP device memory of the current device; the
+ *    caller owns them and keeps them alive until the call returns (solve) or
+ *    until phicomb_poll returns something other than PHICOMB_PENDING.
+ *  - Matrices are row-major.  V is [n][p+1] in natural order v_0..v_p; W is
+ *    [n][r].  Everything is IEEE double unless stated.
+ *  - The spectral shift is called xi* in the paper (Sec. 3, Algorithm 1); the
+ *    field is named "shift".  (The paper's mu is the undo factor
+ *    exp(t xi/s) of Sec. 3, eq. (rec.F.shift); it is internal.)
+ *  - Handles are opaque and owned by the library.  An operator handle may be
+ *    used by several threads; calls on one handle are serialised.
+ */
+#ifndef PHICOMB_H
+#define PHICOMB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PHICOMB_OK 0
+#define PHICOMB_PENDING 1
+#define PHICOMB_EINVAL (-1)    /* bad argument: sizes, non-finite input, tol<=0, ceil(s max|t|) > INT_MAX */
+#define PHICOMB_ENOMEM (-2)    /* device allocation failed */
+#define PHICOMB_EADMIT (-3)    /* request can never fit the serving memory budget */
+#define PHICOMB_ENOCONV (-4)   /* a Taylor loop hit the term cap (150 terms) */
+#define PHICOMB_EOVERFLOW (-5) /* Algorithm 1 accepted no power of A (||Av|| beyond the overflow guard) */
+#define PHICOMB_EDEVICE (-6)   /* HIP runtime error, missing device, or a non-finite result */
+
+/* precision of the Taylor terms (the parameter search is always FP64) */
+#define PHICOMB_FP64 0
+#define PHICOMB_MIXED 1  /* FP32 terms and products, FP64 stopping test and cross-step carry */
+
+/* limits of this build */
+#define PHICOMB_MAX_P 7  /* p <= 7 */
+#define PHICOMB_MAX_R 4  /* r <= 4 */
+#define PHICOMB_MAX_M 100
+
+typedef struct phicomb_op_s *phicomb_op;
+typedef struct phicomb_req_s *phicomb_req;
+
+/* Result of Algorithm 1 (Sec. 3).  Plain data: may be stored and reused for
+ * every later solve with the same operator (Sec. 6: the pair is computed once
+ * and reused across calls). */
+typedef struct {
+    double shift;    /* xi*, minimiser of the power objective f (Alg. 1) */
+    double s0;       /* preliminary scale from the last accepted growth ratios */
+    double zstar;    /* minimiser in the reduced variable z = -xi/s0 */
+    double fstar;    /* f(xi*) */
+    double s;        /* real scaling parameter s = s0 f(xi*) / (tol m!)^(1/m) */
+    double tol;      /* tolerance the pair was chosen for */
+    int32_t m;       /* Taylor degree used by the objective (default 61) */
+    int32_t r_acc;   /* last accepted power of the guarded basis */
+    int32_t n_feval; /* objective evaluations spent by Brent's method */
+    int32_t status;  /* PHICOMB_OK when valid */
+} phicomb_params_t;
+
+/* Per-solve statistics. */
+typedef struct {
+    int32_t s_int;          /* integer scaling max(1, ceil(s max|t_i|)) (Alg. 3) */
+    int32_t terms_S;        /* k at exit of the S-series loop (Alg. 3, rec.D) */
+    int32_t terms_rec;      /* Taylor terms summed over the s_int-1 recovery steps */
+    int32_t max_terms_step; /* largest term count of one recovery step */
+    int32_t status;
+    int32_t fp32_terms;     /* mixed precision: recovery terms evaluated in FP32 */
+    double bytes_alg;       /* algorithmic HBM bytes of the solve (see design notes) */
+    double ms;              /* device time of the solve kernel, milliseconds */
+} phicomb_stats_t;
+
+/* ---------------------------------------------------------------- operators
+ * An operator is copied to the current HIP device and stays resident until
+ * phicomb_op_destroy.  Products are the only access to A (Alg. 1-3 take "a
+ * matrix or linear operator"); the library applies A - xi I with the shift
+ * folded into the diagonal.
+ */
+
+/* CSR matrix, host arrays: rowptr[n+1] (rowptr[0] = 0, non-decreasing),
+ * col[nnz] in [0, n), val[nnz].  n >= 1, nnz < 2^31.  EINVAL on a malformed
+ * structure or a non-finite value. */
+int phicomb_op_create_csr(int64_t n, const int32_t *rowptr, const int32_t *col,
+                          const double *val, phicomb_op *out);
+
+/* Constant-coefficient stencil on a Dirichlet grid.  dim = 2 (5-point, grid =
+ * {nx, ny, 1}) or 3 (7-point, grid = {nx, ny, nz}); grid index i = x + nx*(y +
+ * ny*z).  coef[7] = {centre, -x, +x, -y, +y, -z, +z} neighbour weights;
+ * superdiag is added to every matrix entry (i, i+1), i < n-1 (a non-normal
+ * perturbation; at the end of a grid line it is a new entry).  n = nx*ny*nz
+ * must be < 2^31. */
+int phicomb_op_create_stencil(int dim, const int32_t grid[3], const double coef[7],
+                              double superdiag, phicomb_op *out);
+
+/* Dense n x n matrix, host row-major.  Products use FP64 MFMA. */
+int phicomb_op_create_dense(int64_t n, const double *A, phicomb_op *out);
+
+int phicomb_op_destroy(phicomb_op op);
+int64_t phicomb_op_n(phicomb_op op);
+
+/* ---------------------------------------------------------------- Algorithm 1
+ * Choose the shift xi* and the scaling s for tolerance tol and degree m
+ * (Sec. 3, Algorithm 1): guarded power basis of a unit vector, preliminary
+ * scale s0, normalised basis extended to degree m, Brent minimisation of
+ * f(xi) = ||(A - xi I)^m v||^(1/m) / s0 over z = -xi/s0 in [-sqrt(n), sqrt(n)],
+ * then s = s0 f(xi*) / (tol m!)^(1/m).
+ *   v      host [n] start vector (normalised by the library), or NULL for the
+ *          library's own deterministic vector derived from seed
+ *          (SplitMix64 of (seed, i) mapped to [-1, 1)).
+ *   m      1..PHICOMB_MAX_M (the paper's default is 61).
+ *   stream hipStream_t or NULL; the call is blocking.
+ * Errors: EINVAL, EOVERFLOW (no power accepted), ENOMEM, EDEVICE.
+ * A zero operator returns shift 0, s 1. */
+int phicomb_params(phicomb_op op, double tol, int m, const double *v, uint64_t seed,
+                   void *stream, phicomb_params_t *out);
+
+/* ---------------------------------------------------------------- Algorithm 3
+ * W[:, i] = sum_j beta[i][j] phi_j(t_i A) v_j, i < r (Sec. 4, Algorithm 3, the
+ * block variant; r = 1 is Algorithm 2).  Blocking: returns when W is written.
+ *   prm       result of phicomb_params for this operator (any tol).
+ *   p, r      0 <= p <= PHICOMB_MAX_P, 1 <= r <= PHICOMB_MAX_R.
+ *   t         host [r] abscissae (any sign, finite).
+ *   beta      host [r][p+1] weights; the paper's case is beta[i][j] = alpha_i^j.
+ *   V         device [n][p+1] row-major, double.
+ *   tol       stopping tolerance of the Taylor loops (stopTm), > 0.
+ *   precision PHICOMB_FP64 or PHICOMB_MIXED.
+ *   W         device [n][r] row-major, double, written.
+ *   stream    hipStream_t or NULL.
+ *   stats     optional, may be NULL.
+ * p = 0 returns exp(t_i A) v_0; v_0 = 0 returns sum_{j>=1} beta_ij phi_j v_j.
+ * Errors: EINVAL, ENOCONV, ENOMEM, EDEVICE (W then undefined). */
+int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r,
+                  const double *t, const double *beta, const void *V, double tol,
+                  int precision, void *W, void *stream, phicomb_stats_t *stats);
+
+/* ---------------------------------------------------------------- serving
+ * Asynchronous form of phicomb_solve for a request stream (continuous
+ * batching).  The request is admitted when its device footprint fits the
+ * budget set by phicomb_serve_config and a slot is free; admitted requests of
+ * any operator run concurrently on the device.  Same arguments as
+ * phicomb_solve minus the stream.  V and W must stay valid until poll
+ * reports completion.  EADMIT if the request can never fit. */
+int phicomb_submit(phicomb_op op, const phicomb_params_t *prm, int p, int r,
+                   const double *t, const double *beta, const void *V, double tol,
+                   int precision, void *W, phicomb_req *out);
+
+/* PHICOMB_PENDING while queued or running; otherwise the request's final
+ * status, with stats filled (optional) and the ticket released. */
+int phicomb_poll(phicomb_req req, phicomb_stats_t *stats);
+
+/* Serving limits: device bytes the admitted requests may hold at once, and
+ * the number of requests that may run concurrently (slots). */
+int phicomb_serve_config(int64_t budget_bytes, int slots);
+
+/* Device footprint in bytes of one request (V, W and work blocks). */
+int64_t phicomb_request_bytes(int64_t n, int p, int r, int precision);
+
+const char *phicomb_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHICOMB_H */

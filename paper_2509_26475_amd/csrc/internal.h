@@ -1,0 +1,397 @@
+// Internal declarations of the phicomb HIP library (gfx950).
+//
+// Device-side building blocks shared by the kernels: operator row products
+// (stencil, CSR), wave64 reductions, the grid barrier of the persistent
+// kernels, and the host-side op/workspace structures.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "phicomb.h"
+
+namespace phc {
+
+constexpr int kWG = 256;                      // threads per workgroup (four wave64)
+constexpr int kWaves = kWG / 64;
+constexpr int kPMax1 = PHICOMB_MAX_P + 1;     // p + 1 <= 8
+constexpr int kRMax = PHICOMB_MAX_R;          // r <= 4
+constexpr int kTermCap = 150;                 // Taylor terms per loop
+constexpr long kSpinLimit = 1L << 27;         // barrier wait bound (~10 s), then EDEVICE
+
+enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2 };
+
+// Operator as seen by the kernels (passed by value).
+struct DevOp {
+    int kind;
+    int dim;
+    int nx, ny, nz;
+    int pad;
+    int64_t n;
+    double c[7];          // stencil: centre, -x, +x, -y, +y, -z, +z
+    double superdiag;     // stencil: added on (i, i+1), i < n-1
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *dense;  // row-major n x n
+};
+
+// ------------------------------------------------------------ reductions
+// Max of non-negative doubles; a NaN operand wins so that it reaches the
+// stopping test and is reported.
+__device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = nmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------ grid barrier
+// Barrier of a cooperative (co-resident) grid, grouped by XCD.
+//
+// Each XCD has its own L2, and an agent-scope release (L2 write-back) or
+// acquire (L2 invalidate) acts on the whole L2 of the XCD that issues it, so
+// one release and one acquire per XCD suffice.  Workgroups register in the
+// group of the XCD they run on (hardware register XCC_ID) once, in
+// grid_setup.  In grid_sync every workgroup waits for its own stores
+// (workgroup release) and arrives at its group counter; the last arrival of a
+// group (the leader) writes the XCD's L2 back and arrives at the top counter;
+// the last leader opens the top generation; each leader then invalidates its
+// XCD's L2 and opens its group's generation; members invalidate their CU's L1
+// and continue.  Members cannot write between their leader's write-back and
+// invalidate, so no dirty line is dropped.  Every wait is bounded; a timeout
+// returns false and the kernel reports PHICOMB_EDEVICE.
+constexpr int kLineU = 64;              // uint32 per 256-byte line
+constexpr int kSyncLines = 64;          // size of the sync area in lines
+constexpr int kSyncBytes = kSyncLines * kLineU * 4;
+enum : int {
+    kLnTop = 0, kLnTopGen = 1, kLnSetup = 2, kLnSetupFlag = 3,
+    kLnGroup = 4,        // 16 group counters
+    kLnGroupGen = 20,    // 16 group generations
+    kLnGroupSize = 36,   // 16 group sizes
+};
+
+struct GridSync {
+    unsigned *bar;
+    unsigned xcc, gsize, ngroups, gen;
+};
+
+__device__ __forceinline__ unsigned hw_xcc_id() {
+    // HW_REG_XCC_ID (hwreg 20), bits [3:0]
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;
+}
+
+__device__ __forceinline__ bool spin_until_ne(const unsigned *p, unsigned v) {
+    long spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == v) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit)
+            return false;
+    }
+    return true;
+}
+
+// One-time flat, fully fenced registration barrier; thread 0 fills gs.
+__device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned x = hw_xcc_id();
+        atomicAdd(bar + kLineU * (kLnGroupSize + x), 1u);
+        __threadfence();
+        const unsigned prev = atomicAdd(bar + kLineU * kLnSetup, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            __hip_atomic_store(bar + kLineU * kLnSetupFlag, 1u, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else if (!spin_until_ne(bar + kLineU * kLnSetupFlag, 0u)) {
+            ok = 0;
+        }
+        __threadfence();
+        unsigned ng = 0;
+        for (int k = 0; k < 16; ++k)
+            ng += __hip_atomic_load(bar + kLineU * (kLnGroupSize + k), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        gs.bar = bar;
+        gs.xcc = x;
+        gs.gsize = __hip_atomic_load(bar + kLineU * (kLnGroupSize + x), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        gs.ngroups = ng;
+        gs.gen = 0;
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+__device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = gs.gen;
+        unsigned *bar = gs.bar;
+        unsigned *gc = bar + kLineU * (kLnGroup + gs.xcc);
+        unsigned *gg = bar + kLineU * (kLnGroupGen + gs.xcc);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gs.gsize - 1) {
+            __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned top = __hip_atomic_fetch_add(bar + kLineU * kLnTop, 1u,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (top == gs.ngroups - 1) {
+                __hip_atomic_store(bar + kLineU * kLnTop, 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(bar + kLineU * kLnTopGen, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!spin_until_ne(bar + kLineU * kLnTopGen, g))
+                ok = 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(gg, g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (!spin_until_ne(gg, g))
+                ok = 0;
+            // invalidate this CU's vector L1 (the leader invalidated the L2)
+            __asm__ volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        }
+        gs.gen = g + 1;
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+// Workgroup max of NV values into part[blockIdx.x*2 + j] (plain stores,
+// published by the next grid_sync).
+template <int NV, int NT>
+__device__ __forceinline__ void store_partials(double (&v)[NV], double *part, double (*red)[2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = wave_max(v[j]);
+    __syncthreads();   // every wave has finished reading red from the last exchange
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            red[wave][j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double m = red[0][j];
+            for (int w = 1; w < NT / 64; ++w)
+                m = nmax(m, red[w][j]);
+            part[blockIdx.x * 2 + j] = m;
+        }
+    }
+}
+
+// Max over all workgroups' partials, after grid_sync; every thread gets it.
+template <int NV, int NT>
+__device__ __forceinline__ void load_partials(const double *part, unsigned nblocks,
+                                              double (&out)[NV], double (*red)[2]) {
+    double m[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        m[j] = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += NT) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            m[j] = nmax(m[j], part[b * 2 + j]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        m[j] = wave_max(m[j]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            red[wave][j] = m[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double r = red[0][j];
+        for (int w = 1; w < NT / 64; ++w)
+            r = nmax(r, red[w][j]);
+        out[j] = r;
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical block ids so that neighbouring rows share an
+// L2 slice.
+__device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
+    if (nblocks % 8 != 0)
+        return b;
+    return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+// ------------------------------------------------------------ operator rows
+// Everything about one output row that does not depend on the column block.
+struct RowCtx {
+    int64_t i;
+    int q0, q1;          // CSR range
+    unsigned mask;       // stencil neighbours present: bit0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z
+    double cxp;          // stencil +x weight including the superdiagonal
+};
+
+template <int KIND>
+__device__ __forceinline__ RowCtx row_ctx(const DevOp &A, int64_t row) {
+    RowCtx rc;
+    rc.i = row;
+    if constexpr (KIND == kStencil) {
+        const int r32 = (int)row;
+        const int x = r32 % A.nx;
+        const int yz = r32 / A.nx;
+        const int y = yz % A.ny;
+        const int z = yz / A.ny;
+        unsigned m = 0;
+        m |= (x > 0) ? 1u : 0u;
+        const bool xp = x < A.nx - 1;
+        const bool sd = (row < A.n - 1) && (A.superdiag != 0.0);
+        m |= (xp || sd) ? 2u : 0u;
+        m |= (y > 0) ? 4u : 0u;
+        m |= (y < A.ny - 1) ? 8u : 0u;
+        if (A.dim == 3) {
+            m |= (z > 0) ? 16u : 0u;
+            m |= (z < A.nz - 1) ? 32u : 0u;
+        }
+        rc.mask = m;
+        rc.cxp = (xp ? A.c[2] : 0.0) + (sd ? A.superdiag : 0.0);
+        rc.q0 = rc.q1 = 0;
+    } else {
+        rc.q0 = A.rowptr[row];
+        rc.q1 = A.rowptr[row + 1];
+        rc.mask = 0;
+        rc.cxp = 0.0;
+    }
+    return rc;
+}
+
+// Load of element `idx` of a column, addressed as a wave-uniform base plus a
+// 32-bit byte offset (columns are shorter than 2^28 elements), so the load
+// needs a single offset VGPR instead of a 64-bit address pair.
+__device__ __forceinline__ double ld_col(const double *__restrict__ base, unsigned idx) {
+    return *(const double *)((const char *)base + (idx << 3));
+}
+
+// y[j] = (A X)(i, col0+j) - shift * X(i, col0+j), j < NC.
+// X is column-major: column c at X + c*ld.
+template <int KIND, int NC>
+__device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
+                                           const double *__restrict__ X, int64_t ld, int col0,
+                                           double shift, double (&y)[NC]) {
+    const double *__restrict__ cb[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        cb[j] = X + (int64_t)(col0 + j) * ld;
+    const unsigned i = (unsigned)rc.i;
+    if constexpr (KIND == kStencil) {
+        const double cc = A.c[0] - shift;
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+            y[j] = cc * ld_col(cb[j], i);
+        if (rc.mask & 1u) {
+            const unsigned q = i - 1u;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += A.c[1] * ld_col(cb[j], q);
+        }
+        if (rc.mask & 2u) {
+            const unsigned q = i + 1u;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += rc.cxp * ld_col(cb[j], q);
+        }
+        const unsigned sy = (unsigned)A.nx;
+        if (rc.mask & 4u) {
+            const unsigned q = i - sy;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += A.c[3] * ld_col(cb[j], q);
+        }
+        if (rc.mask & 8u) {
+            const unsigned q = i + sy;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += A.c[4] * ld_col(cb[j], q);
+        }
+        const unsigned sz = (unsigned)A.nx * (unsigned)A.ny;
+        if (rc.mask & 16u) {
+            const unsigned q = i - sz;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += A.c[5] * ld_col(cb[j], q);
+        }
+        if (rc.mask & 32u) {
+            const unsigned q = i + sz;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += A.c[6] * ld_col(cb[j], q);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+            y[j] = 0.0;
+        for (int q = rc.q0; q < rc.q1; ++q) {
+            const double a = A.val[q];
+            const unsigned c = (unsigned)A.col[q];
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += a * ld_col(cb[j], c);
+        }
+        if (shift != 0.0) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] -= shift * ld_col(cb[j], i);
+        }
+    }
+}
+
+// ------------------------------------------------------------ host side
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace phc
+
+struct phicomb_op_s {
+    phc::DevOp dev;
+    int device = 0;
+    int64_t nnz = 0;
+    void *mem = nullptr;          // device storage of the operator
+    std::mutex mu;                // serialises solves on this operator
+    phc::Workspace ws;            // grow-only workspace of blocking solves
+    double *pinned = nullptr;     // small pinned host buffer for read-backs
+};
+
+namespace phc {
+// implemented in solve.hip
+int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+               const double *beta, const void *V, double tol, void *W, hipStream_t stream,
+               phicomb_stats_t *stats, void *ws, size_t ws_bytes, double *pinned);
+size_t solve_workspace_bytes(int64_t n, int p, int r, int precision);
+// implemented in params.hip
+int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed,
+                hipStream_t stream, phicomb_params_t *out);
+// implemented in api.cpp
+int ensure_workspace(phicomb_op op, size_t bytes);
+}  // namespace phc

@@ -1,0 +1,217 @@
+// Request serving: admission by device footprint, concurrent execution of
+// admitted requests on their own streams, completion by polling.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "internal.h"
+
+using namespace phc;
+
+struct phicomb_req_s {
+    phicomb_op op;
+    phicomb_params_t prm;
+    int p, r, precision;
+    double t[PHICOMB_MAX_R];
+    double beta[PHICOMB_MAX_R * (PHICOMB_MAX_P + 1)];
+    const void *V;
+    void *W;
+    double tol;
+    int64_t bytes;
+    std::atomic<int> state{0};   // 0 queued, 1 running, 2 done
+    int status = PHICOMB_PENDING;
+    phicomb_stats_t stats{};
+};
+
+namespace {
+
+struct Worker {
+    std::thread th;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    double *pinned = nullptr;
+};
+
+class Server {
+  public:
+    static Server &get() {
+        static Server s;
+        return s;
+    }
+
+    int configure(int64_t budget, int slots) {
+        std::lock_guard<std::mutex> g(mu_);
+        if (budget > 0)
+            budget_ = budget;
+        if (slots > 0)
+            want_slots_ = slots;
+        return PHICOMB_OK;
+    }
+
+    int submit(phicomb_req req) {
+        std::unique_lock<std::mutex> g(mu_);
+        if (req->bytes > budget_)
+            return PHICOMB_EADMIT;
+        start_workers_locked();
+        queue_.push_back(req);
+        cv_.notify_all();
+        return PHICOMB_OK;
+    }
+
+  private:
+    Server() {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+            budget_ = (int64_t)(free_b / 2);
+        else
+            budget_ = (int64_t)1 << 33;
+        device_ = 0;
+        hipGetDevice(&device_);
+    }
+
+    void start_workers_locked() {
+        while ((int)workers_.size() < want_slots_) {
+            workers_.emplace_back(new Worker());
+            Worker *w = workers_.back();
+            w->th = std::thread([this, w]() { run(w); });
+            w->th.detach();
+        }
+    }
+
+    // First request in arrival order whose footprint fits the free budget.
+    phicomb_req take_locked() {
+        for (auto it = queue_.begin(); it != queue_.end(); ++it) {
+            if (in_use_ + (*it)->bytes <= budget_) {
+                phicomb_req q = *it;
+                queue_.erase(it);
+                in_use_ += q->bytes;
+                return q;
+            }
+        }
+        return nullptr;
+    }
+
+    void run(Worker *w) {
+        hipSetDevice(device_);
+        hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+        hipHostMalloc((void **)&w->pinned, 64 * sizeof(double), hipHostMallocDefault);
+        for (;;) {
+            phicomb_req q = nullptr;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&]() { return (q = take_locked()) != nullptr; });
+            }
+            q->state.store(1);
+            const size_t need = solve_workspace_bytes(q->op->dev.n, q->p, q->r, q->precision);
+            int st = PHICOMB_OK;
+            if (w->ws_bytes < need) {
+                if (w->ws)
+                    hipFree(w->ws);
+                w->ws = nullptr;
+                w->ws_bytes = 0;
+                if (hipMalloc(&w->ws, need) != hipSuccess)
+                    st = PHICOMB_ENOMEM;
+                else
+                    w->ws_bytes = need;
+            }
+            if (st == PHICOMB_OK)
+                st = solve_fp64(q->op, &q->prm, q->p, q->r, q->t, q->beta, q->V, q->tol, q->W,
+                                w->stream, &q->stats, w->ws, w->ws_bytes, w->pinned);
+            q->stats.status = st;
+            q->status = st;
+            {
+                std::lock_guard<std::mutex> g(mu_);
+                in_use_ -= q->bytes;
+            }
+            q->state.store(2);
+            cv_.notify_all();
+        }
+    }
+
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<phicomb_req> queue_;
+    std::vector<Worker *> workers_;
+    int64_t budget_ = 0, in_use_ = 0;
+    int want_slots_ = 4;
+    int device_ = 0;
+};
+
+bool finite_array(const double *a, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]))
+            return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t phicomb_request_bytes(int64_t n, int p, int r, int precision) {
+    if (n < 1 || p < 0 || r < 1)
+        return -1;
+    return (int64_t)solve_workspace_bytes(n, p, r, precision) + 8 * n * (p + 1 + r);
+}
+
+int phicomb_serve_config(int64_t budget_bytes, int slots) {
+    if (slots > 64)
+        return PHICOMB_EINVAL;
+    return Server::get().configure(budget_bytes, slots);
+}
+
+int phicomb_submit(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+                   const double *beta, const void *V, double tol, int precision, void *W,
+                   phicomb_req *out) {
+    if (!op || !prm || !t || !beta || !V || !W || !out)
+        return PHICOMB_EINVAL;
+    if (p < 0 || p > PHICOMB_MAX_P || r < 1 || r > PHICOMB_MAX_R)
+        return PHICOMB_EINVAL;
+    if (!(tol > 0.0) || !std::isfinite(tol) || prm->status != PHICOMB_OK)
+        return PHICOMB_EINVAL;
+    if (!finite_array(t, r) || !finite_array(beta, (int64_t)r * (p + 1)))
+        return PHICOMB_EINVAL;
+    if (precision != PHICOMB_FP64 && precision != PHICOMB_MIXED)
+        return PHICOMB_EINVAL;
+    phicomb_req q = new (std::nothrow) phicomb_req_s();
+    if (!q)
+        return PHICOMB_ENOMEM;
+    q->op = op;
+    q->prm = *prm;
+    q->p = p;
+    q->r = r;
+    q->precision = precision;
+    std::memcpy(q->t, t, sizeof(double) * r);
+    std::memcpy(q->beta, beta, sizeof(double) * r * (p + 1));
+    q->V = V;
+    q->W = W;
+    q->tol = tol;
+    q->bytes = phicomb_request_bytes(op->dev.n, p, r, precision);
+    const int st = Server::get().submit(q);
+    if (st != PHICOMB_OK) {
+        delete q;
+        return st;
+    }
+    *out = q;
+    return PHICOMB_OK;
+}
+
+int phicomb_poll(phicomb_req req, phicomb_stats_t *stats) {
+    if (!req)
+        return PHICOMB_EINVAL;
+    if (req->state.load() != 2)
+        return PHICOMB_PENDING;
+    const int st = req->status;
+    if (stats)
+        *stats = req->stats;
+    delete req;
+    return st;
+}
+
+}  // extern "C"
