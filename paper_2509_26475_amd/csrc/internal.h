@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -232,6 +233,22 @@ __device__ __forceinline__ void load_partials(const double *part, unsigned nbloc
             r = nmax(r, red[w][j]);
         out[j] = r;
     }
+}
+
+// Launch of a persistent kernel whose grid never exceeds the co-resident
+// capacity (occupancy x CUs, computed by the caller).  The default is an
+// ordinary launch: the blocking entry points own the device while they run,
+// and the barrier's bounded wait turns a grid that is not fully resident
+// into PHICOMB_EDEVICE instead of a hang.  PHICOMB_LAUNCH=cooperative asks
+// the runtime for the co-residency guarantee instead.
+inline hipError_t launch_persistent(const void *fn, unsigned grid, unsigned block, void **args,
+                                    hipStream_t stream) {
+    static const bool coop = [] {
+        const char *e = getenv("PHICOMB_LAUNCH");
+        return e && e[0] == 'c';
+    }();
+    return coop ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, stream)
+                : hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, stream);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a

@@ -1,4 +1,5 @@
-// Parameter selection (Al-Mohy, Sec. 3, Algorithm 1) on the device, FP64.
+// Parameter selection (Al-Mohy, Sec. 3, Algorithm 1) on the device, FP64, in
+// one persistent kernel.
 //
 //   V_0 = v/||v||_2;  W_k = A V_{k-1}, L_k = log||W_k||_2, accepted while
 //   L_k + log(k+1)/2 + max_j log binom(m,j) <= 0.8 log(realmax) and
@@ -8,12 +9,13 @@
 //   minimised by Brent's method over z in [-sqrt(n), sqrt(n)];
 //   s = s0 f(xi*) / (tol m!)^(1/m).
 //
-// The basis lives on the device as [m+1][n] (column-major), each product and
-// each objective evaluation is one fused pass that also forms a deterministic
-// scaled sum of squares (per thread, per wave in a fixed shuffle tree, per
-// workgroup, then over workgroups in index order), so repeated runs give
-// identical parameters.  The host keeps only the scalar logic: the guard,
-// s0, and Brent's iteration.
+// The basis is [m+1][n] (column-major).  Each 2-norm is a scaled sum of
+// squares (scale, ssq) merged per thread, per wave in a fixed shuffle tree,
+// per workgroup in wave order, and finally over all workgroups in index
+// order by every workgroup on its own, so all threads hold the same value,
+// take the same guard and Brent decisions, and repeated runs give identical
+// parameters.  Brent's iteration runs redundantly in every thread; each
+// objective evaluation is one pass over the basis plus one grid exchange.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -23,7 +25,8 @@
 
 namespace phc {
 
-constexpr int kNormBlocks = 1024;
+constexpr int kPNT = 512;          // threads per workgroup
+constexpr int kPMaxGrid = 4096;
 
 // (scale, ssq) pair: value = scale * sqrt(ssq), scale = max |x| seen.
 struct Ssq {
@@ -65,178 +68,254 @@ __device__ __forceinline__ Ssq wave_ssq(Ssq v) {
         Ssq o;
         o.scale = __shfl_xor(v.scale, off, 64);
         o.ssq = __shfl_xor(v.ssq, off, 64);
-        // combine in a lane-independent order so both partners agree
+        // both partners merge (lower lane, upper lane) in the same order
         const bool lower = (threadIdx.x & off) == 0;
         v = lower ? ssq_merge(v, o) : ssq_merge(o, v);
     }
     return v;
 }
 
-__device__ __forceinline__ void block_ssq_store(Ssq v, double2 *part) {
-    __shared__ double sc[kWaves], sq[kWaves];
-    v = wave_ssq(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        sc[wave] = v.scale;
-        sq[wave] = v.ssq;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Ssq acc{sc[0], sq[0]};
-        for (int w = 1; w < kWaves; ++w)
-            acc = ssq_merge(acc, Ssq{sc[w], sq[w]});
-        part[blockIdx.x] = make_double2(acc.scale, acc.ssq);
-    }
+__device__ __forceinline__ double ssq_log(Ssq s) {
+    return (s.scale == 0.0) ? -INFINITY : log(s.scale) + 0.5 * log(s.ssq);
 }
 
-// Combine the per-workgroup partials in index order; out = {log||x||, ||x||}.
-__global__ void ssq_final(const double2 *part, int nparts, double *out) {
-    __shared__ double sc[kWG], sq[kWG];
-    const int t = threadIdx.x;
-    Ssq acc{0.0, 0.0};
-    for (int b = t; b < nparts; b += kWG)   // fixed assignment, fixed order
-        acc = ssq_merge(acc, Ssq{part[b].x, part[b].y});
-    sc[t] = acc.scale;
-    sq[t] = acc.ssq;
-    __syncthreads();
-    if (t == 0) {
-        Ssq tot{0.0, 0.0};
-        for (int w = 0; w < kWG; ++w)
-            tot = ssq_merge(tot, Ssq{sc[w], sq[w]});
-        if (tot.scale == 0.0) {
-            out[0] = -INFINITY;
-            out[1] = 0.0;
-        } else {
-            out[0] = log(tot.scale) + 0.5 * log(tot.ssq);
-            out[1] = tot.scale * sqrt(tot.ssq);
-        }
-    }
-}
+struct ParamsArgs {
+    DevOp op;
+    int64_t n;
+    int m, have_v, brent_maxit, pad;
+    uint64_t seed;
+    double tol, gmax, gmin, lmax, zmax, brent_rel, brent_abs;
+    const double *binom;   // [m+1] exact binomials (device)
+    double *basis;      // [m+1][n]
+    unsigned *bar;      // sync area
+    double *part;       // [2][kPMaxGrid][2]
+    double *out;        // 16 values, see params_fp64
+};
 
-// y = (A x) * scale  and its partial 2-norm.
-template <int KIND>
-__global__ __launch_bounds__(kWG) void spmv_norm(DevOp A, const double *__restrict__ x,
-                                                 double *__restrict__ y, double scale,
-                                                 double2 *part) {
-    const int64_t n = A.n;
-    Ssq acc{0.0, 0.0};
-    for (int64_t row = (int64_t)blockIdx.x * kWG + threadIdx.x; row < n;
-         row += (int64_t)gridDim.x * kWG) {
-        const RowCtx rc = row_ctx<KIND>(A, row);
-        double v[1];
-        apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, v);
-        const double w = (scale == 1.0) ? v[0] : v[0] / scale;
-        y[row] = w;
-        ssq_add(acc, w);
-    }
-    block_ssq_store(acc, part);
-}
-
-// x <- x * f   or  x <- x / d (only one of the two is used)
-__global__ void scale_vec(double *x, int64_t n, double f, double d) {
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
-        x[i] = (d != 0.0) ? x[i] / d : x[i] * f;
-}
-
-__global__ void norm_only(const double *__restrict__ x, int64_t n, double2 *part) {
-    Ssq acc{0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
-        ssq_add(acc, x[i]);
-    block_ssq_store(acc, part);
+__global__ void params_sync_init(unsigned *bar, double *out) {
+    for (int i = threadIdx.x; i < kSyncLines * kLineU; i += blockDim.x)
+        bar[i] = 0u;
+    if (threadIdx.x < 16)
+        out[threadIdx.x] = 0.0;
 }
 
 // SplitMix64 (Steele, Lea & Flood, 2014) of (seed, i), mapped to [-1, 1).
-__global__ void fill_splitmix(double *x, int64_t n, uint64_t seed) {
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
-        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z = z ^ (z >> 31);
-        x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+__device__ __forceinline__ double splitmix_unit(uint64_t seed, int64_t i) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
+    __shared__ double wsc[kPNT / 64], wsq[kPNT / 64];
+    __shared__ double coef[PHICOMB_MAX_M + 1];
+    __shared__ int ok_lds;
+    const unsigned G = gridDim.x;
+    const int lb = xcd_logical_block(blockIdx.x, G);
+    const int64_t n = P.n;
+    const int64_t chunk = (n + G - 1) / G;
+    const int64_t lo = std::min<int64_t>(n, (int64_t)lb * chunk);
+    const int64_t hi = std::min<int64_t>(n, lo + chunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = P.m;
+    const DevOp &A = P.op;
+    double *basis = P.basis;
+    auto col = [&](int k) { return basis + (int64_t)k * n; };
+    auto finish = [&](double status, double r, double s0, double zs, double fs, double shift,
+                      double s, double nfev) {
+        if (blockIdx.x == 0 && tid == 0) {
+            double *o = P.out;
+            o[0] = status; o[1] = r; o[2] = s0; o[3] = zs; o[4] = fs; o[5] = shift;
+            o[6] = s; o[7] = nfev;
+        }
+    };
+
+    GridSync gs;
+    if (!grid_setup(gs, P.bar, &ok_lds)) {
+        finish(PHICOMB_EDEVICE, 0, 0, 0, 0, 0, 0, 0);
+        return;
     }
-}
+    unsigned epoch = 0;
+    bool alive = true;
+    // Deterministic global 2-norm: every workgroup ends with the same value.
+    auto exchange = [&](Ssq v) __attribute__((always_inline)) -> Ssq {
+        v = wave_ssq(v);
+        __syncthreads();
+        if (lane == 0) {
+            wsc[wave] = v.scale;
+            wsq[wave] = v.ssq;
+        }
+        __syncthreads();
+        double *pt = P.part + (size_t)(epoch & 1) * 2 * kPMaxGrid;
+        if (tid == 0) {
+            Ssq acc{wsc[0], wsq[0]};
+            for (int w = 1; w < kPNT / 64; ++w)
+                acc = ssq_merge(acc, Ssq{wsc[w], wsq[w]});
+            pt[blockIdx.x * 2] = acc.scale;
+            pt[blockIdx.x * 2 + 1] = acc.ssq;
+        }
+        if (!grid_sync(gs, &ok_lds))
+            alive = false;
+        Ssq acc{0.0, 0.0};
+        for (unsigned b = tid; b < G; b += kPNT)
+            acc = ssq_merge(acc, Ssq{pt[b * 2], pt[b * 2 + 1]});
+        acc = wave_ssq(acc);
+        __syncthreads();
+        if (lane == 0) {
+            wsc[wave] = acc.scale;
+            wsq[wave] = acc.ssq;
+        }
+        __syncthreads();
+        Ssq tot{wsc[0], wsq[0]};
+        for (int w = 1; w < kPNT / 64; ++w)
+            tot = ssq_merge(tot, Ssq{wsc[w], wsq[w]});
+        ++epoch;
+        return tot;
+    };
 
-// y_i = sum_k c_k V_k[i] (ascending k) and its partial 2-norm.
-struct Coef {
-    double c[PHICOMB_MAX_M + 1];
-};
-
-__global__ __launch_bounds__(kWG) void objective_norm(const double *__restrict__ basis,
-                                                      int64_t n, int m, Coef cf, double2 *part) {
-    Ssq acc{0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
-        double y = 0.0;
-        for (int k = 0; k <= m; ++k)
-            y += cf.c[k] * basis[(int64_t)k * n + i];
-        ssq_add(acc, y);
+    // ---- V_0 = v / ||v||
+    if (!P.have_v)
+        for (int64_t row = lo + tid; row < hi; row += kPNT)
+            basis[row] = splitmix_unit(P.seed, row);
+    Ssq a{0.0, 0.0};
+    for (int64_t row = lo + tid; row < hi; row += kPNT)
+        ssq_add(a, basis[row]);
+    const Ssq vs = exchange(a);
+    const double nv = vs.scale * sqrt(vs.ssq);
+    if (!alive) {
+        finish(PHICOMB_EDEVICE, 0, 0, 0, 0, 0, 0, 0);
+        return;
     }
-    block_ssq_store(acc, part);
-}
+    if (!(nv > 0.0) || !(nv <= DBL_MAX)) {
+        finish(PHICOMB_EINVAL, 0, 0, 0, 0, 0, 0, 0);
+        return;
+    }
 
-// ------------------------------------------------------------------ host
-namespace {
+    // ---- guarded powers W_k = A V_{k-1}
+    double Lh[7];   // L_{k-6} .. L_k, newest last
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        Lh[j] = 0.0;
+    int r = 0;
+    double L1 = 0.0;
+    for (int k = 1; k <= m; ++k) {
+        const double *x = col(k - 1);
+        double *y = col(k);
+        Ssq acc{0.0, 0.0};
+        for (int64_t row = lo + tid; row < hi; row += kPNT) {
+            const RowCtx rc = row_ctx<KIND>(A, row);
+            double w[1];
+            apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
+            const double val = (k == 1) ? w[0] / nv : w[0];   // A (v/||v||)
+            y[row] = val;
+            ssq_add(acc, val);
+        }
+        const double Lk = ssq_log(exchange(acc));
+        if (!alive) {
+            finish(PHICOMB_EDEVICE, 0, 0, 0, 0, 0, 0, 0);
+            return;
+        }
+        if (k == 1) {
+            L1 = Lk;
+            for (int64_t row = lo + tid; row < hi; row += kPNT)   // nobody reads V_0 again
+                basis[row] = basis[row] / nv;
+        }
+        if (Lk != Lk) {
+            finish(PHICOMB_EINVAL, 0, 0, 0, 0, 0, 0, 0);
+            return;
+        }
+        if (Lk + 0.5 * log(k + 1.0) + P.lmax > P.gmax || Lk < P.gmin)
+            break;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            Lh[j] = Lh[j + 1];
+        Lh[6] = Lk;
+        r = k;
+    }
+    if (r == 0) {
+        if (L1 < P.gmin)   // A v vanishes: A is treated as zero
+            finish(PHICOMB_OK, 0, 0, 0, 0, 0, 1.0, 0);
+        else
+            finish(PHICOMB_EOVERFLOW, 0, 0, 0, 0, 0, 0, 0);
+        return;
+    }
+    // s0 from the last accepted ratios L_{j+1} - L_j, j = jr .. r-1 (Lh[6] = L_r)
+    double s0;
+    if (r >= 3) {
+        const int jr = std::max(2, r - 5);
+        const int cnt = r - jr;   // 1..5 ratios L_{j+1} - L_j, j = jr .. r-1
+        double sum = 0.0;
+#pragma unroll
+        for (int d = 5; d >= 1; --d)   // d = r - j, so ascending j
+            if (d <= cnt)
+                sum += Lh[7 - d] - Lh[6 - d];
+        s0 = exp(sum / (double)cnt);
+    } else {
+        s0 = exp(Lh[6] / (double)r);
+    }
+    // ---- normalise V_j by s0^-j, then extend to degree m
+    const double ls0 = log(s0);
+    for (int j = 1; j <= r; ++j) {
+        const double sc = exp(-(double)j * ls0);
+        double *v = col(j);
+        for (int64_t row = lo + tid; row < hi; row += kPNT)
+            v[row] = v[row] * sc;
+    }
+    for (int k = r + 1; k <= m; ++k) {
+        if (!grid_sync(gs, &ok_lds)) {
+            finish(PHICOMB_EDEVICE, r, s0, 0, 0, 0, 0, 0);
+            return;
+        }
+        const double *x = col(k - 1);
+        double *y = col(k);
+        for (int64_t row = lo + tid; row < hi; row += kPNT) {
+            const RowCtx rc = row_ctx<KIND>(A, row);
+            double w[1];
+            apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
+            y[row] = w[0] / s0;
+        }
+    }
 
-struct Ctx {
-    phicomb_op op;
-    hipStream_t st;
-    double2 *part;
-    double *res;      // device [2]
-    double *pinned;   // host [2]
-    int nb;
-};
+    // ---- objective f(z) = ||sum_k b_k z^(m-k) V_k||^(1/m); every row of the
+    //      basis read here was written by this same thread
+    auto objective = [&](double z) __attribute__((always_inline)) -> double {
+        __syncthreads();
+        if (tid <= m) {
+            double pw = 1.0;   // z^(m-k), built by repeated multiplication
+            for (int e = 0; e < m - tid; ++e)
+                pw = pw * z;
+            coef[tid] = P.binom[tid] * pw;
+        }
+        __syncthreads();
+        Ssq acc{0.0, 0.0};
+        for (int64_t row = lo + tid; row < hi; row += kPNT) {
+            double y = 0.0;
+            for (int k = 0; k <= m; ++k)
+                y += coef[k] * basis[(int64_t)k * n + row];
+            ssq_add(acc, y);
+        }
+        const Ssq tot = exchange(acc);
+        return (tot.scale == 0.0) ? 0.0 : exp(ssq_log(tot) / (double)m);
+    };
 
-int readback(Ctx &c, double *lognorm, double *norm) {
-    ssq_final<<<1, kWG, 0, c.st>>>(c.part, c.nb, c.res);
-    if (hipMemcpyAsync(c.pinned, c.res, 2 * sizeof(double), hipMemcpyDeviceToHost, c.st) !=
-        hipSuccess)
-        return PHICOMB_EDEVICE;
-    if (hipStreamSynchronize(c.st) != hipSuccess)
-        return PHICOMB_EDEVICE;
-    if (lognorm)
-        *lognorm = c.pinned[0];
-    if (norm)
-        *norm = c.pinned[1];
-    return PHICOMB_OK;
-}
-
-void launch_spmv(Ctx &c, const double *x, double *y, double scale) {
-    const DevOp &A = c.op->dev;
-    if (A.kind == kStencil)
-        spmv_norm<kStencil><<<c.nb, kWG, 0, c.st>>>(A, x, y, scale, c.part);
-    else
-        spmv_norm<kCsr><<<c.nb, kWG, 0, c.st>>>(A, x, y, scale, c.part);
-}
-
-double binom_double(int m, int k) {
-    // exact integer in 128 bits, then one correctly rounded conversion
-    unsigned __int128 b = 1;
-    if (k > m - k)
-        k = m - k;
-    for (int j = 1; j <= k; ++j)
-        b = b * (unsigned __int128)(m - k + j) / (unsigned __int128)j;
-    return (double)b;
-}
-
-// Brent's minimiser without derivatives (Brent 1973, ch. 5): golden-section
-// search accelerated by parabolic interpolation through the best three
-// points.  Returns false if an evaluation failed.
-template <class F>
-bool brent_minimise(F &&f, double lo, double hi, double rel, double abs_tol, int max_iter,
-                    double *xmin, double *fmin, int *nfev) {
-    const double gs = 0.3819660112501051;   // (3 - sqrt 5)/2
-    double x = lo + gs * (hi - lo), w = x, v = x;
-    double fx;
-    if (!f(x, &fx))
-        return false;
+    // ---- Brent's minimiser without derivatives (Brent 1973, ch. 5):
+    //      golden-section steps accelerated by parabolic interpolation.
+    const double gsr = 0.3819660112501051;   // (3 - sqrt 5)/2
+    double blo = -P.zmax, bhi = P.zmax;
+    double x = blo + gsr * (bhi - blo), w = x, v = x;
+    double fx = objective(x);
     double fw = fx, fv = fx, step = 0.0, prev = 0.0;
     int evals = 1;
-    for (int it = 0; it < max_iter; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        const double tol1 = rel * std::fabs(x) + abs_tol;
-        if (std::fabs(x - mid) <= 2.0 * tol1 - 0.5 * (hi - lo))
+    for (int it = 0; it < P.brent_maxit && alive; ++it) {
+        const double mid = 0.5 * (blo + bhi);
+        const double tol1 = P.brent_rel * fabs(x) + P.brent_abs;
+        if (fabs(x - mid) <= 2.0 * tol1 - 0.5 * (bhi - blo))
             break;
         bool golden = true;
-        if (std::fabs(prev) > tol1) {
+        if (fabs(prev) > tol1) {
             const double r1 = (x - w) * (fx - fv);
             double q = (x - v) * (fx - fw);
             double pp = (x - v) * q - (x - w) * r1;
@@ -247,51 +326,80 @@ bool brent_minimise(F &&f, double lo, double hi, double rel, double abs_tol, int
                 q = -q;
             const double older = prev;
             prev = step;
-            if (std::fabs(pp) < std::fabs(0.5 * q * older) && pp > q * (lo - x) &&
-                pp < q * (hi - x)) {
+            if (fabs(pp) < fabs(0.5 * q * older) && pp > q * (blo - x) && pp < q * (bhi - x)) {
                 step = pp / q;
                 const double u = x + step;
-                if (u - lo < 2.0 * tol1 || hi - u < 2.0 * tol1)
+                if (u - blo < 2.0 * tol1 || bhi - u < 2.0 * tol1)
                     step = (x < mid) ? tol1 : -tol1;
                 golden = false;
             }
         }
         if (golden) {
-            prev = (x < mid) ? hi - x : lo - x;
-            step = gs * prev;
+            prev = (x < mid) ? bhi - x : blo - x;
+            step = gsr * prev;
         }
-        const double u = (std::fabs(step) >= tol1) ? x + step : x + (step > 0.0 ? tol1 : -tol1);
-        double fu;
-        if (!f(u, &fu))
-            return false;
+        const double u = (fabs(step) >= tol1) ? x + step : x + (step > 0.0 ? tol1 : -tol1);
+        const double fu = objective(u);
         ++evals;
         if (fu <= fx) {
-            (u < x ? hi : lo) = x;
-            v = w;
-            fv = fw;
-            w = x;
-            fw = fx;
-            x = u;
-            fx = fu;
+            if (u < x)
+                bhi = x;
+            else
+                blo = x;
+            v = w; fv = fw;
+            w = x; fw = fx;
+            x = u; fx = fu;
         } else {
-            (u < x ? lo : hi) = u;
+            if (u < x)
+                blo = u;
+            else
+                bhi = u;
             if (fu <= fw || w == x) {
-                v = w;
-                fv = fw;
-                w = u;
-                fw = fu;
+                v = w; fv = fw;
+                w = u; fw = fu;
             } else if (fu <= fv || v == x || v == w) {
-                v = u;
-                fv = fu;
+                v = u; fv = fu;
             }
         }
     }
-    *xmin = x;
-    *fmin = fx;
-    *nfev = evals;
-    return true;
+    if (!alive) {
+        finish(PHICOMB_EDEVICE, r, s0, 0, 0, 0, 0, 0);
+        return;
+    }
+    // s = s0 f* / (tol m!)^(1/m) is formed on the host
+    finish(PHICOMB_OK, r, s0, x, fx, -x * s0, 0.0, evals);
 }
 
+// ------------------------------------------------------------------ host
+namespace {
+double binom_double(int m, int k) {
+    // exact integer in 128 bits, then one correctly rounded conversion
+    unsigned __int128 b = 1;
+    if (k > m - k)
+        k = m - k;
+    for (int j = 1; j <= k; ++j)
+        b = b * (unsigned __int128)(m - k + j) / (unsigned __int128)j;
+    return (double)b;
+}
+
+int max_params_grid(int kind, int device) {
+    static std::mutex mu;
+    static int cached[2][64] = {};
+    std::lock_guard<std::mutex> g(mu);
+    int &c = cached[kind == kStencil ? 0 : 1][device & 63];
+    if (c > 0)
+        return c;
+    const void *fn = (kind == kStencil) ? (const void *)params_kernel<kStencil>
+                                        : (const void *)params_kernel<kCsr>;
+    int per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPNT, 0) != hipSuccess ||
+        hipGetDeviceProperties(&prop, device) != hipSuccess || per_cu < 1)
+        return 0;
+    // one workgroup per CU: the barrier cost grows with the number of workgroups
+    c = std::min(prop.multiProcessorCount, kPMaxGrid);
+    return c;
+}
 }  // namespace
 
 // Brent settings of the parameter search (tolerances in z = -xi/s0).
@@ -299,137 +407,81 @@ constexpr double kBrentRel = 1.4901161193847656e-08;
 constexpr double kBrentAbs = 1e-6;
 constexpr int kBrentMaxIt = 100;
 
+size_t params_workspace_bytes(int64_t n, int m) {
+    return (size_t)kSyncBytes + sizeof(double) * (4 * kPMaxGrid + 32 + 128) +
+           sizeof(double) * (size_t)n * (size_t)(m + 1);
+}
+
 int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed,
                 hipStream_t stream, phicomb_params_t *out) {
     const int64_t n = op->dev.n;
     std::memset(out, 0, sizeof(*out));
     out->m = m;
     out->tol = tol;
-    double *basis = nullptr;
-    double2 *part = nullptr;
-    double *res = nullptr;
-    if (hipMalloc(&basis, sizeof(double) * (size_t)n * (m + 1)) != hipSuccess)
-        return PHICOMB_ENOMEM;
-    if (hipMalloc(&part, sizeof(double2) * kNormBlocks) != hipSuccess ||
-        hipMalloc(&res, 4 * sizeof(double)) != hipSuccess) {
-        hipFree(basis);
-        hipFree(part);
-        return PHICOMB_ENOMEM;
-    }
-    int nb = (int)std::min<int64_t>(kNormBlocks, (n + kWG - 1) / kWG);
-    Ctx c{op, stream, part, res, op->pinned, nb};
-    int status = PHICOMB_OK;
-    auto cleanup = [&]() {
-        hipStreamSynchronize(stream);
-        hipFree(basis);
-        hipFree(part);
-        hipFree(res);
-    };
-    // V_0 = v / ||v||
-    if (v) {
-        if (hipMemcpyAsync(basis, v, sizeof(double) * n, hipMemcpyHostToDevice, stream) !=
-            hipSuccess) {
-            cleanup();
-            return PHICOMB_EDEVICE;
-        }
-    } else {
-        fill_splitmix<<<nb, kWG, 0, stream>>>(basis, n, seed);
-    }
-    norm_only<<<nb, kWG, 0, stream>>>(basis, n, part);
-    double lv = 0.0, nv = 0.0;
-    if ((status = readback(c, &lv, &nv)) != PHICOMB_OK) {
-        cleanup();
-        return status;
-    }
-    if (!(nv > 0.0) || !std::isfinite(nv)) {
-        cleanup();
-        return PHICOMB_EINVAL;
-    }
-    scale_vec<<<nb, kWG, 0, stream>>>(basis, n, 1.0, nv);
-
-    const double gmax = 0.8 * std::log(DBL_MAX);
-    const double gmin = 0.8 * std::log(DBL_MIN);
+    int st = ensure_workspace(op, params_workspace_bytes(n, m));
+    if (st != PHICOMB_OK)
+        return st;
+    char *base = (char *)op->ws.ptr;
+    ParamsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.op = op->dev;
+    a.n = n;
+    a.m = m;
+    a.have_v = v ? 1 : 0;
+    a.seed = seed;
+    a.tol = tol;
+    a.gmax = 0.8 * std::log(DBL_MAX);
+    a.gmin = 0.8 * std::log(DBL_MIN);
     double lmax = -INFINITY;
     for (int j = 0; j <= m; ++j)
         lmax = std::max(lmax, std::lgamma(m + 1.0) - std::lgamma(j + 1.0) - std::lgamma(m - j + 1.0));
-    std::vector<double> L(m + 2, 0.0);
-    int r = 0;
-    for (int k = 1; k <= m; ++k) {
-        launch_spmv(c, basis + (size_t)(k - 1) * n, basis + (size_t)k * n, 1.0);
-        double lk = 0.0;
-        if ((status = readback(c, &lk, nullptr)) != PHICOMB_OK) {
-            cleanup();
-            return status;
-        }
-        L[k] = lk;
-        if (std::isnan(lk)) {
-            cleanup();
-            return PHICOMB_EINVAL;
-        }
-        if (lk + 0.5 * std::log(k + 1.0) + lmax > gmax || lk < gmin)
-            break;
-        r = k;
-    }
-    out->r_acc = r;
-    if (r == 0) {
-        cleanup();
-        if (L[1] < gmin) {   // A v vanishes: treat A as zero
-            out->shift = 0.0;
-            out->s = 1.0;
-            out->status = PHICOMB_OK;
-            return PHICOMB_OK;
-        }
-        return PHICOMB_EOVERFLOW;
-    }
-    double s0;
-    if (r >= 3) {
-        const int jr = std::max(2, r - 5);
-        double sum = 0.0;
-        for (int j = jr; j <= r - 1; ++j)
-            sum += L[j + 1] - L[j];
-        s0 = std::exp(sum / (double)(r - jr));
-    } else {
-        s0 = std::exp(L[r] / (double)r);
-    }
-    out->s0 = s0;
-    const double ls0 = std::log(s0);
-    for (int j = 1; j <= r; ++j)
-        scale_vec<<<nb, kWG, 0, stream>>>(basis + (size_t)j * n, n, std::exp(-(double)j * ls0), 0.0);
-    for (int k = r + 1; k <= m; ++k)
-        launch_spmv(c, basis + (size_t)(k - 1) * n, basis + (size_t)k * n, s0);
-
-    std::vector<double> bino(m + 1);
+    a.lmax = lmax;
+    a.zmax = std::sqrt((double)n);
+    a.brent_rel = kBrentRel;
+    a.brent_abs = kBrentAbs;
+    a.brent_maxit = kBrentMaxIt;
+    a.bar = (unsigned *)base;
+    a.part = (double *)(base + kSyncBytes);
+    a.out = a.part + 4 * kPMaxGrid;
+    double *bin_dev = a.part + 4 * kPMaxGrid + 16;
+    a.binom = bin_dev;
+    a.basis = (double *)(base + kSyncBytes + sizeof(double) * (4 * kPMaxGrid + 32 + 128));
+    double bin_host[PHICOMB_MAX_M + 1];
     for (int k = 0; k <= m; ++k)
-        bino[k] = binom_double(m, k);
-    auto f = [&](double z, double *fz) -> bool {
-        Coef cf;
-        double pw = 1.0;
-        for (int k = m; k >= 0; --k) {
-            cf.c[k] = bino[k] * pw;
-            pw = pw * z;
-        }
-        objective_norm<<<nb, kWG, 0, stream>>>(basis, n, m, cf, part);
-        double ln = 0.0, nr = 0.0;
-        if (readback(c, &ln, &nr) != PHICOMB_OK)
-            return false;
-        *fz = (nr == 0.0) ? 0.0 : std::exp(ln / (double)m);
-        return true;
-    };
-    const double zmax = std::sqrt((double)n);
-    double zs = 0.0, fz = 0.0;
-    int nfev = 0;
-    if (!brent_minimise(f, -zmax, zmax, kBrentRel, kBrentAbs, kBrentMaxIt, &zs, &fz, &nfev)) {
-        cleanup();
+        bin_host[k] = binom_double(m, k);
+    if (hipMemcpyAsync(bin_dev, bin_host, sizeof(double) * (m + 1), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
         return PHICOMB_EDEVICE;
-    }
-    out->zstar = zs;
-    out->shift = -zs * s0;
-    out->fstar = fz;
-    out->n_feval = nfev;
-    out->s = s0 * fz / std::exp((std::log(tol) + std::lgamma(m + 1.0)) / (double)m);
-    out->status = PHICOMB_OK;
-    cleanup();
-    return PHICOMB_OK;
+    if (v && hipMemcpyAsync(a.basis, v, sizeof(double) * n, hipMemcpyHostToDevice, stream) !=
+                 hipSuccess)
+        return PHICOMB_EDEVICE;
+    const int maxg = max_params_grid(op->dev.kind, op->device);
+    if (maxg < 1)
+        return PHICOMB_EDEVICE;
+    const int64_t G = std::min<int64_t>(maxg, (n + kPNT - 1) / kPNT);
+    const void *fn = (op->dev.kind == kStencil) ? (const void *)params_kernel<kStencil>
+                                                : (const void *)params_kernel<kCsr>;
+    params_sync_init<<<1, 256, 0, stream>>>(a.bar, a.out);
+    void *args[] = {&a};
+    if (launch_persistent(fn, (unsigned)G, kPNT, args, stream) != hipSuccess)
+        return PHICOMB_EDEVICE;
+    if (hipMemcpyAsync(op->pinned, a.out, 8 * sizeof(double), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return PHICOMB_EDEVICE;
+    const double *o = op->pinned;
+    const int status = (int)o[0];
+    out->r_acc = (int)o[1];
+    out->s0 = o[2];
+    out->zstar = o[3];
+    out->fstar = o[4];
+    out->shift = o[5];
+    out->s = o[6];
+    if (status == PHICOMB_OK && out->r_acc > 0)
+        out->s = out->s0 * out->fstar / std::exp((std::log(tol) + std::lgamma(m + 1.0)) / (double)m);
+    out->n_feval = (int)o[7];
+    out->status = status;
+    return status;
 }
 
 }  // namespace phc

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
     }
     unsigned epoch = 0;
     // publish this workgroup's maxima, cross the barrier, reduce all of them
-    auto exchange = [&](auto &v) -> bool {
+    auto exchange = [&](auto &v) __attribute__((always_inline)) -> bool {
         constexpr int NV = std::extent<std::remove_reference_t<decltype(v)>>::value;
         double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
         store_partials<NV, kNT>(v, pt, red);
@@ -594,8 +594,7 @@ int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const d
     if (timed)
         hipEventRecord(e0, stream);
     void *args[] = {&a};
-    hipError_t le = hipLaunchCooperativeKernel((const void *)fn, dim3((unsigned)G), dim3(kNT),
-                                               args, 0, stream);
+    hipError_t le = launch_persistent((const void *)fn, (unsigned)G, kNT, args, stream);
     if (le != hipSuccess) {
         if (timed) {
             hipEventDestroy(e0);
