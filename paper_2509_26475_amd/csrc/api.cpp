@@ -69,6 +69,10 @@ int upload_csr(phicomb_op op, int64_t n, const int32_t *rowptr, const int32_t *c
         hipFree(mem);
         return PHICOMB_EDEVICE;
     }
+    int maxrow = 0;
+    for (int64_t i = 0; i < n; ++i)
+        maxrow = std::max(maxrow, rowptr[i + 1] - rowptr[i]);
+    op->dev.max_row_nnz = maxrow;
     op->mem = mem;
     op->nnz = nnz;
     op->dev.kind = kCsr;

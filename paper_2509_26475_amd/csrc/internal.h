@@ -23,7 +23,8 @@ constexpr int kRMax = PHICOMB_MAX_R;          // r <= 4
 constexpr int kTermCap = 150;                 // Taylor terms per loop
 constexpr long kSpinLimit = 1L << 27;         // barrier wait bound (~10 s), then EDEVICE
 
-enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2 };
+enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2, kCsrCached = 3 };
+constexpr int kCacheNnz = 8;   // CSR rows up to this length can live in registers
 
 // Operator as seen by the kernels (passed by value).
 struct DevOp {
@@ -38,6 +39,8 @@ struct DevOp {
     const int32_t *col;
     const double *val;
     const double *dense;  // row-major n x n
+    int max_row_nnz;      // CSR: longest row
+    int pad2;
 };
 
 // ------------------------------------------------------------ reductions
@@ -104,8 +107,14 @@ __device__ __forceinline__ bool spin_until_ne(const unsigned *p, unsigned v) {
     return true;
 }
 
+// Every wave waits until its own global stores are acknowledged by the L2
+// before the workgroup arrives (s_barrier alone does not wait for them), so
+// the leader's L2 write-back covers them.
+__device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
 // One-time flat, fully fenced registration barrier; thread 0 fills gs.
 __device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_lds) {
+    wait_own_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
@@ -138,6 +147,7 @@ __device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_
 }
 
 __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
+    wait_own_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
@@ -379,6 +389,50 @@ __device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
             for (int j = 0; j < NC; ++j)
                 y[j] -= shift * ld_col(cb[j], i);
         }
+    }
+}
+
+// A CSR row of at most kCacheNnz entries held in registers for a whole
+// solve (the operator never changes between Taylor terms).
+struct CachedRow {
+    unsigned col[kCacheNnz];
+    double val[kCacheNnz];
+    int cnt;
+};
+
+__device__ __forceinline__ void load_cached_row(const DevOp &A, int64_t row, CachedRow &cr) {
+    const int q0 = A.rowptr[row], q1 = A.rowptr[row + 1];
+    cr.cnt = q1 - q0;
+#pragma unroll
+    for (int k = 0; k < kCacheNnz; ++k) {
+        const bool in = k < cr.cnt;
+        cr.col[k] = in ? (unsigned)A.col[q0 + k] : (unsigned)row;
+        cr.val[k] = in ? A.val[q0 + k] : 0.0;
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void apply_cached(const CachedRow &cr, unsigned i,
+                                             const double *__restrict__ X, int64_t ld, int col0,
+                                             double shift, double (&y)[NC]) {
+    const double *__restrict__ cb[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        cb[j] = X + (int64_t)(col0 + j) * ld;
+        y[j] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kCacheNnz; ++k) {
+        if (k < cr.cnt) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] += cr.val[k] * ld_col(cb[j], cr.col[k]);
+        }
+    }
+    if (shift != 0.0) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+            y[j] -= shift * ld_col(cb[j], i);
     }
 }
 

@@ -132,6 +132,25 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
         }
     };
 
+    // Operator rows: CSR rows of at most kCacheNnz entries stay in registers
+    // for the whole solve; other kinds rebuild their row context per product.
+    constexpr bool CACHED = (KIND == kCsrCached);
+    CachedRow crow[CACHED ? RPT : 1];
+    if constexpr (CACHED)
+        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+            load_cached_row(A, row, crow[decltype(q)::value]);
+        });
+    auto opr = [&](int64_t row, auto q, const double *X, int col0, double shift,
+                   auto &y) __attribute__((always_inline)) {
+        constexpr int NC = std::extent<std::remove_reference_t<decltype(y)>>::value;
+        if constexpr (CACHED) {
+            apply_cached<NC>(crow[decltype(q)::value], (unsigned)row, X, n, col0, shift, y);
+        } else {
+            const RowCtx rc = row_ctx<KIND>(A, row);
+            apply_cols<KIND, NC>(A, rc, X, n, col0, shift, y);
+        }
+    };
+
     GridSync gs;
     if (!grid_setup(gs, P.bar, &ok_lds)) {
         finish(PHICOMB_EDEVICE, 0, 0, 0);
@@ -214,8 +233,7 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
         const double *Uo = par ? P.U1 : P.U0;
         double *Un = par ? P.U0 : P.U1;
         double mx[2] = {0.0, 0.0};
-        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto) {
-            const RowCtx rc = row_ctx<KIND>(A, row);
+        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             double vr[kPMax1];   // reordered v: vr[b] = v_perm(b)(row)
 #pragma unroll
             for (int b = 0; b < kPMax1; ++b)
@@ -224,7 +242,7 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
 #pragma unroll 1
             for (int b = 0; b < P1; ++b) {
                 double y[R];
-                apply_cols<KIND, R>(A, rc, Uo, n, b * R, P.xi, y);
+                opr(row, q, Uo, b * R, P.xi, y);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     double jt;
@@ -271,9 +289,8 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
     {
         double mx[1] = {0.0};
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
-            const RowCtx rc = row_ctx<KIND>(A, row);
             double y[R];
-            apply_cols<KIND, R>(A, rc, P.S, n, 0, 0.0, y);
+            opr(row, q, P.S, 0, 0.0, y);
             const double v0 = P.V[row * P1];
             double f1[R], f2[R];
 #pragma unroll
@@ -332,9 +349,8 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
             double *Fn = par ? P.U0 : P.U1;
             double mx[2] = {0.0, 0.0};
             for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
-                const RowCtx rc = row_ctx<KIND>(A, row);
                 double y[2 * R];
-                apply_cols<KIND, 2 * R>(A, rc, Fo, n, 0, P.xi, y);
+                opr(row, q, Fo, 0, P.xi, y);
                 double sf = 0.0, se = 0.0;
 #pragma unroll
                 for (int c = 0; c < 2 * R; ++c) {
@@ -418,16 +434,22 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
 // ---------------------------------------------------------------- host side
 using KernelFn = void (*)(SolveArgs);
 
+// Instantiated variants: rows per thread 1..8 (register-cached CSR rows:
+// 1..4); larger counts spill and are served by the E-in-memory variant.
 template <int KIND, int R>
 static KernelFn pick_rpt(int rpt, bool emem) {
-    if (emem)
-        return solve_kernel<KIND, R, 1, true>;
+    if constexpr (KIND != kCsrCached) {
+        if (emem)
+            return solve_kernel<KIND, R, 1, true>;
+    }
     switch (rpt) {
     case 1: return solve_kernel<KIND, R, 1, false>;
     case 2: return solve_kernel<KIND, R, 2, false>;
     case 4: return solve_kernel<KIND, R, 4, false>;
-    case 8: return solve_kernel<KIND, R, 8, false>;
-    case 16: return solve_kernel<KIND, R, 16, false>;
+    case 8:
+        if constexpr (KIND != kCsrCached)
+            return solve_kernel<KIND, R, 8, false>;
+        return nullptr;
     default: return nullptr;
     }
 }
@@ -448,6 +470,8 @@ static KernelFn pick_kernel(int kind, int r, int rpt, bool emem) {
         return pick_r<kStencil>(r, rpt, emem);
     if (kind == kCsr)
         return pick_r<kCsr>(r, rpt, emem);
+    if (kind == kCsrCached && !emem)
+        return pick_r<kCsrCached>(r, rpt, false);
     return nullptr;
 }
 
@@ -555,7 +579,7 @@ int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const d
 
     // Variant choice: at most one workgroup per CU (the barrier cost grows
     // with the number of workgroups), then the fewest rows per thread of
-    // {1, 2, 4, 8, 16} that covers n with E in registers and no register
+    // {1, 2, 4, 8} that covers n with E in registers and no register
     // spills; otherwise E moves to memory and rows are grid-strided.
     KernelFn fn = nullptr;
     int64_t G = 0;
@@ -566,10 +590,12 @@ int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const d
         if (hipGetDeviceProperties(&prop, op->device) == hipSuccess)
             cus = prop.multiProcessorCount;
     }
-    for (int rpt : {1, 2, 4, 8, 16}) {
-        KernelFn f = pick_kernel(op->dev.kind, r, rpt, false);
+    const int kind = (op->dev.kind == kCsr && op->dev.max_row_nnz <= kCacheNnz) ? kCsrCached
+                                                                                  : op->dev.kind;
+    for (int rpt : {1, 2, 4, 8}) {
+        KernelFn f = pick_kernel(kind, r, rpt, false);
         if (!f)
-            return PHICOMB_EINVAL;
+            continue;
         hipFuncAttributes fa;
         if (hipFuncGetAttributes(&fa, (const void *)f) != hipSuccess || fa.localSizeBytes > 0)
             continue;
@@ -583,6 +609,8 @@ int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const d
     }
     if (!fn) {
         fn = pick_kernel(op->dev.kind, r, 1, true);
+        if (!fn)
+            return PHICOMB_EINVAL;
         const int maxg = max_coresident(fn, op->device);
         if (maxg < 1)
             return PHICOMB_EDEVICE;
