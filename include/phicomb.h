@@ -48,7 +48,16 @@ extern "C" {
 
 /* precision of the Taylor terms (the parameter search is always FP64) */
 #define PHICOMB_FP64 0
-#define PHICOMB_MIXED 1  /* FP32 terms and products, FP64 stopping test and cross-step carry */
+/* Mixed: in the recovery steps after the first, once the previous Taylor
+ * term's block norm is below tol / (80 u32) (u32 = 2^-24) of the smaller of
+ * the partial sum and the step's starting block, later terms and their
+ * products with A are FP32.  The S-series, the first recovery step, partial
+ * sums, the stopping test and everything carried from one step to the next
+ * stay FP64, so the result agrees with FP64 to about 10 tol in the block
+ * norm.  Terms stay FP64 when the partial sum is outside [1e-20,
+ * 1e30 / (||A||_inf + |xi|)] (FP32 range).  Shapes with no mixed kernel run
+ * FP64. */
+#define PHICOMB_MIXED 1
 
 /* limits of this build */
 #define PHICOMB_MAX_P 7  /* p <= 7 */
@@ -151,11 +160,18 @@ int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r,
 
 /* ---------------------------------------------------------------- serving
  * Asynchronous form of phicomb_solve for a request stream (continuous
- * batching).  The request is admitted when its device footprint fits the
- * budget set by phicomb_serve_config and a slot is free; admitted requests of
- * any operator run concurrently on the device.  Same arguments as
- * phicomb_solve minus the stream.  V and W must stay valid until poll
- * reports completion.  EADMIT if the request can never fit. */
+ * batching; the paper computes the parameters once per operator and reuses
+ * them across calls, Sec. 6).  A request is admitted, in arrival order
+ * except that one waiting for memory does not block smaller ones behind it,
+ * as soon as its device footprint (phicomb_request_bytes) fits what the
+ * running requests leave of the budget and a slot is free.  Admitted
+ * requests of any operator run at the same time on their own streams; each
+ * is guaranteed CUs/slots of the device's CUs and takes up to one CU per 512
+ * rows when more are free.  The result of a request does not depend on what
+ * runs beside it.  Same arguments as phicomb_solve minus the stream.  V and W
+ * must stay valid, and the operator alive, until poll reports completion.
+ * Returns at once: OK with *out set, EINVAL, ENOMEM, or EADMIT if the
+ * request can never fit the budget. */
 int phicomb_submit(phicomb_op op, const phicomb_params_t *prm, int p, int r,
                    const double *t, const double *beta, const void *V, double tol,
                    int precision, void *W, phicomb_req *out);
@@ -164,8 +180,11 @@ int phicomb_submit(phicomb_op op, const phicomb_params_t *prm, int p, int r,
  * status, with stats filled (optional) and the ticket released. */
 int phicomb_poll(phicomb_req req, phicomb_stats_t *stats);
 
-/* Serving limits: device bytes the admitted requests may hold at once, and
- * the number of requests that may run concurrently (slots). */
+/* Serving limits: device bytes the admitted requests may hold at once
+ * (budget_bytes <= 0 keeps the current one; default half of the free device
+ * memory at the first call), and the number of requests that may run
+ * concurrently (slots, 1..64, <= 0 keeps the current one; default 4).  Slots
+ * can grow but not shrink once requests have run (EINVAL). */
 int phicomb_serve_config(int64_t budget_bytes, int slots);
 
 /* Device footprint in bytes of one request (V, W and work blocks). */

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <new>
 
@@ -70,9 +71,16 @@ int upload_csr(phicomb_op op, int64_t n, const int32_t *rowptr, const int32_t *c
         return PHICOMB_EDEVICE;
     }
     int maxrow = 0;
-    for (int64_t i = 0; i < n; ++i)
+    double norm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
         maxrow = std::max(maxrow, rowptr[i + 1] - rowptr[i]);
+        double sr = 0.0;
+        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+            sr += std::fabs(val[q]);
+        norm = std::max(norm, sr);
+    }
     op->dev.max_row_nnz = maxrow;
+    op->norm_inf = norm;
     op->mem = mem;
     op->nnz = nnz;
     op->dev.kind = kCsr;
@@ -86,6 +94,61 @@ int upload_csr(phicomb_op op, int64_t n, const int32_t *rowptr, const int32_t *c
 }  // namespace
 
 namespace phc {
+namespace {
+struct Ledger {
+    std::mutex mu;
+    std::condition_variable cv;
+    int total = -1, free = 0;
+};
+constexpr int kMaxDevices = 64;
+Ledger g_ledger[kMaxDevices];
+
+Ledger &ledger(int device) { return g_ledger[device & (kMaxDevices - 1)]; }
+}  // namespace
+
+int device_cus(int device) {
+    static std::mutex mu;
+    static int cache[kMaxDevices] = {};
+    std::lock_guard<std::mutex> g(mu);
+    int &c = cache[device & (kMaxDevices - 1)];
+    if (c == 0) {
+        hipDeviceProp_t prop;
+        c = (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+                ? prop.multiProcessorCount
+                : 1;
+    }
+    return c;
+}
+
+int cu_acquire(int device, int want, int min_grant) {
+    const int total = device_cus(device) / kXcds * kXcds;
+    if (total < kXcds)
+        return 0;
+    want = std::min(round_xcd(std::max(1, want)), total);
+    min_grant = std::min(round_xcd(std::max(1, min_grant)), want);
+    Ledger &l = ledger(device);
+    std::unique_lock<std::mutex> g(l.mu);
+    if (l.total < 0) {
+        l.total = total;
+        l.free = total;
+    }
+    l.cv.wait(g, [&]() { return l.free >= min_grant; });
+    const int got = std::min(want, l.free / kXcds * kXcds);
+    l.free -= got;
+    return got;
+}
+
+void cu_release(int device, int n) {
+    if (n <= 0)
+        return;
+    Ledger &l = ledger(device);
+    {
+        std::lock_guard<std::mutex> g(l.mu);
+        l.free = std::min(l.total, l.free + n);
+    }
+    l.cv.notify_all();
+}
+
 int ensure_workspace(phicomb_op op, size_t bytes) {
     if (op->ws.bytes >= bytes)
         return PHICOMB_OK;
@@ -162,6 +225,10 @@ int phicomb_op_create_stencil(int dim, const int32_t grid[3], const double coef[
         op->dev.c[j] = (dim == 2 && j >= 5) ? 0.0 : coef[j];
     op->dev.superdiag = superdiag;
     op->nnz = 0;
+    double norm = std::fabs(superdiag);
+    for (int j = 0; j < 7; ++j)
+        norm += std::fabs(op->dev.c[j]);
+    op->norm_inf = norm;
     *out = op;
     return PHICOMB_OK;
 }
@@ -234,8 +301,8 @@ int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r, cons
     int st = ensure_workspace(op, need);
     if (st != PHICOMB_OK)
         return st;
-    st = solve_fp64(op, prm, p, r, t, beta, V, tol, W, (hipStream_t)stream, stats, op->ws.ptr,
-                    op->ws.bytes, op->pinned);
+    st = solve_run(op, prm, p, r, t, beta, V, tol, precision, W, (hipStream_t)stream, stats,
+                   op->ws.ptr, op->ws.bytes, op->pinned);
     if (stats)
         stats->status = st;
     return st;

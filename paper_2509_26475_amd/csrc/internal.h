@@ -107,6 +107,20 @@ __device__ __forceinline__ bool spin_until_ne(const unsigned *p, unsigned v) {
     return true;
 }
 
+// Agent-scope release and acquire of this XCD's L2, each waited for in the
+// same asm block: the compiler's own fences can emit the write-back without
+// a wait for its completion, and a counter update that overtakes the
+// write-back lets another XCD read this XCD's stale lines.  The acquire also
+// invalidates the CU's vector L1 explicitly: without it a leader's CU kept
+// lines of the buffer it had read two barriers earlier (same parity of the
+// double-buffered terms and partials) and read them back stale.
+__device__ __forceinline__ void l2_writeback() {
+    __asm__ volatile("buffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+__device__ __forceinline__ void l2_invalidate() {
+    __asm__ volatile("buffer_inv sc1\n\tbuffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // Every wave waits until its own global stores are acknowledged by the L2
 // before the workgroup arrives (s_barrier alone does not wait for them), so
 // the leader's L2 write-back covers them.
@@ -120,16 +134,16 @@ __device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_
         int ok = 1;
         const unsigned x = hw_xcc_id();
         atomicAdd(bar + kLineU * (kLnGroupSize + x), 1u);
-        __threadfence();
+        l2_writeback();
         const unsigned prev = atomicAdd(bar + kLineU * kLnSetup, 1u);
         if (prev == gridDim.x - 1) {
-            __threadfence();
-            __hip_atomic_store(bar + kLineU * kLnSetupFlag, 1u, __ATOMIC_RELEASE,
+            l2_writeback();
+            __hip_atomic_store(bar + kLineU * kLnSetupFlag, 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         } else if (!spin_until_ne(bar + kLineU * kLnSetupFlag, 0u)) {
             ok = 0;
         }
-        __threadfence();
+        l2_invalidate();
         unsigned ng = 0;
         for (int k = 0; k < 16; ++k)
             ng += __hip_atomic_load(bar + kLineU * (kLnGroupSize + k), __ATOMIC_RELAXED,
@@ -156,22 +170,21 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
         unsigned *gc = bar + kLineU * (kLnGroup + gs.xcc);
         unsigned *gg = bar + kLineU * (kLnGroupGen + gs.xcc);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        // The counters only ever grow (modulo 2^32): arrival number
+        // (g+1)*size - 1 closes generation g.  Nothing is reset, so an early
+        // arrival at the next barrier can never be overwritten.
         const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == gs.gsize - 1) {
-            __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (prev + 1u == (g + 1u) * gs.gsize) {
+            l2_writeback();
             const unsigned top = __hip_atomic_fetch_add(bar + kLineU * kLnTop, 1u,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (top == gs.ngroups - 1) {
-                __hip_atomic_store(bar + kLineU * kLnTop, 0u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (top + 1u == (g + 1u) * gs.ngroups)
                 __hip_atomic_fetch_add(bar + kLineU * kLnTopGen, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-            }
             if (!spin_until_ne(bar + kLineU * kLnTopGen, g))
                 ok = 0;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            l2_invalidate();
             __hip_atomic_store(gg, g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             if (!spin_until_ne(gg, g))
@@ -315,79 +328,88 @@ __device__ __forceinline__ RowCtx row_ctx(const DevOp &A, int64_t row) {
 // Load of element `idx` of a column, addressed as a wave-uniform base plus a
 // 32-bit byte offset (columns are shorter than 2^28 elements), so the load
 // needs a single offset VGPR instead of a 64-bit address pair.
-__device__ __forceinline__ double ld_col(const double *__restrict__ base, unsigned idx) {
-    return *(const double *)((const char *)base + (idx << 3));
+template <typename T>
+__device__ __forceinline__ T ld_col(const T *__restrict__ base, unsigned idx) {
+    return *(const T *)((const char *)base + idx * (unsigned)sizeof(T));
 }
 
-// y[j] = (A X)(i, col0+j) - shift * X(i, col0+j), j < NC.
-// X is column-major: column c at X + c*ld.
-template <int KIND, int NC>
+// y[j] = (A X)(i, col0+j) - shift * X(i, col0+j), j < NC, with X of element
+// type TX and the products accumulated in TA (double, or float for the
+// reduced-precision terms).  X is column-major: column c at X + c*ld.
+template <int KIND, int NC, typename TX, typename TA>
 __device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
-                                           const double *__restrict__ X, int64_t ld, int col0,
-                                           double shift, double (&y)[NC]) {
-    const double *__restrict__ cb[NC];
+                                           const TX *__restrict__ X, int64_t ld, int col0,
+                                           double shift, TA (&y)[NC]) {
+    const TX *__restrict__ cb[NC];
 #pragma unroll
     for (int j = 0; j < NC; ++j)
         cb[j] = X + (int64_t)(col0 + j) * ld;
     const unsigned i = (unsigned)rc.i;
     if constexpr (KIND == kStencil) {
-        const double cc = A.c[0] - shift;
+        const TA cc = (TA)(A.c[0] - shift);
 #pragma unroll
         for (int j = 0; j < NC; ++j)
-            y[j] = cc * ld_col(cb[j], i);
+            y[j] = cc * (TA)ld_col(cb[j], i);
         if (rc.mask & 1u) {
             const unsigned q = i - 1u;
+            const TA w = (TA)A.c[1];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += A.c[1] * ld_col(cb[j], q);
+                y[j] += w * (TA)ld_col(cb[j], q);
         }
         if (rc.mask & 2u) {
             const unsigned q = i + 1u;
+            const TA w = (TA)rc.cxp;
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += rc.cxp * ld_col(cb[j], q);
+                y[j] += w * (TA)ld_col(cb[j], q);
         }
         const unsigned sy = (unsigned)A.nx;
         if (rc.mask & 4u) {
             const unsigned q = i - sy;
+            const TA w = (TA)A.c[3];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += A.c[3] * ld_col(cb[j], q);
+                y[j] += w * (TA)ld_col(cb[j], q);
         }
         if (rc.mask & 8u) {
             const unsigned q = i + sy;
+            const TA w = (TA)A.c[4];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += A.c[4] * ld_col(cb[j], q);
+                y[j] += w * (TA)ld_col(cb[j], q);
         }
         const unsigned sz = (unsigned)A.nx * (unsigned)A.ny;
         if (rc.mask & 16u) {
             const unsigned q = i - sz;
+            const TA w = (TA)A.c[5];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += A.c[5] * ld_col(cb[j], q);
+                y[j] += w * (TA)ld_col(cb[j], q);
         }
         if (rc.mask & 32u) {
             const unsigned q = i + sz;
+            const TA w = (TA)A.c[6];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += A.c[6] * ld_col(cb[j], q);
+                y[j] += w * (TA)ld_col(cb[j], q);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < NC; ++j)
-            y[j] = 0.0;
+            y[j] = (TA)0;
         for (int q = rc.q0; q < rc.q1; ++q) {
-            const double a = A.val[q];
+            const TA a = (TA)A.val[q];
             const unsigned c = (unsigned)A.col[q];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += a * ld_col(cb[j], c);
+                y[j] += a * (TA)ld_col(cb[j], c);
         }
         if (shift != 0.0) {
+            const TA sh = (TA)shift;
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] -= shift * ld_col(cb[j], i);
+                y[j] -= sh * (TA)ld_col(cb[j], i);
         }
     }
 }
@@ -411,28 +433,30 @@ __device__ __forceinline__ void load_cached_row(const DevOp &A, int64_t row, Cac
     }
 }
 
-template <int NC>
+template <int NC, typename TX, typename TA>
 __device__ __forceinline__ void apply_cached(const CachedRow &cr, unsigned i,
-                                             const double *__restrict__ X, int64_t ld, int col0,
-                                             double shift, double (&y)[NC]) {
-    const double *__restrict__ cb[NC];
+                                             const TX *__restrict__ X, int64_t ld, int col0,
+                                             double shift, TA (&y)[NC]) {
+    const TX *__restrict__ cb[NC];
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
         cb[j] = X + (int64_t)(col0 + j) * ld;
-        y[j] = 0.0;
+        y[j] = (TA)0;
     }
 #pragma unroll
     for (int k = 0; k < kCacheNnz; ++k) {
         if (k < cr.cnt) {
+            const TA a = (TA)cr.val[k];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += cr.val[k] * ld_col(cb[j], cr.col[k]);
+                y[j] += a * (TA)ld_col(cb[j], cr.col[k]);
         }
     }
     if (shift != 0.0) {
+        const TA sh = (TA)shift;
 #pragma unroll
         for (int j = 0; j < NC; ++j)
-            y[j] -= shift * ld_col(cb[j], i);
+            y[j] -= sh * (TA)ld_col(cb[j], i);
     }
 }
 
@@ -448,6 +472,7 @@ struct phicomb_op_s {
     phc::DevOp dev;
     int device = 0;
     int64_t nnz = 0;
+    double norm_inf = 0.0;        // max_i sum_j |a_ij| (bounds FP32 intermediates)
     void *mem = nullptr;          // device storage of the operator
     std::mutex mu;                // serialises solves on this operator
     phc::Workspace ws;            // grow-only workspace of blocking solves
@@ -455,10 +480,27 @@ struct phicomb_op_s {
 };
 
 namespace phc {
+// Workgroup-slot ledger of a device (implemented in api.cpp).  Persistent
+// kernels spin at grid barriers, so two of them that are each only partly
+// resident would wait on each other for ever; every persistent launch of the
+// library therefore first takes its workgroup count from this ledger (one
+// slot per CU, each workgroup fits a CU on its own) and returns it when the
+// kernel has completed.
+// Grants are whole multiples of kXcds: workgroups are dealt to the XCDs in
+// turn, so a grid of G workgroups puts at most ceil(G/8) on any XCD; holding
+// round_xcd(G) slots makes the ledger's bound hold on each XCD's own CUs.
+constexpr int kXcds = 8;
+inline int round_xcd(int64_t g) { return (int)((g + kXcds - 1) / kXcds * kXcds); }
+int device_cus(int device);
+int cu_acquire(int device, int want, int min_grant);   // blocks; returns granted in [min, want]
+void cu_release(int device, int n);
+
 // implemented in solve.hip
-int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
-               const double *beta, const void *V, double tol, void *W, hipStream_t stream,
-               phicomb_stats_t *stats, void *ws, size_t ws_bytes, double *pinned);
+// cu_floor: fewest workgroups the solve accepts (0: one per CU up to n/512).
+int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+              const double *beta, const void *V, double tol, int precision, void *W,
+              hipStream_t stream, phicomb_stats_t *stats, void *ws, size_t ws_bytes,
+              double *pinned, int cu_floor = 0);
 size_t solve_workspace_bytes(int64_t n, int p, int r, int precision);
 // implemented in params.hip
 int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed,

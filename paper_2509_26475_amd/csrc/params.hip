@@ -459,8 +459,15 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     if (maxg < 1)
         return PHICOMB_EDEVICE;
     const int64_t G = std::min<int64_t>(maxg, (n + kPNT - 1) / kPNT);
+    const int held = round_xcd(G);   // at most ceil(G/8) of the grid lands on any XCD
     const void *fn = (op->dev.kind == kStencil) ? (const void *)params_kernel<kStencil>
                                                 : (const void *)params_kernel<kCsr>;
+    if (cu_acquire(op->device, held, held) != held)
+        return PHICOMB_EDEVICE;
+    struct Hold {
+        int dev, g;
+        ~Hold() { cu_release(dev, g); }
+    } hold{op->device, held};
     params_sync_init<<<1, 256, 0, stream>>>(a.bar, a.out);
     void *args[] = {&a};
     if (launch_persistent(fn, (unsigned)G, kPNT, args, stream) != hipSuccess)

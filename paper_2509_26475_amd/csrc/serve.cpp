@@ -1,12 +1,17 @@
-// Request serving: admission by device footprint, concurrent execution of
-// admitted requests on their own streams, completion by polling.
+// Request serving with continuous batching: requests are admitted in arrival
+// order as soon as their device footprint fits the memory budget and a slot
+// is free; admitted solves run at the same time on their own streams, each
+// with a share of the CUs from the device's workgroup-slot ledger; results
+// are collected by polling.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <new>
 #include <thread>
 
 #include "internal.h"
@@ -31,26 +36,30 @@ struct phicomb_req_s {
 namespace {
 
 struct Worker {
-    std::thread th;
     hipStream_t stream = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     double *pinned = nullptr;
 };
 
+// One per process, never destroyed: its worker threads wait on its
+// condition variable until the process ends.
 class Server {
   public:
     static Server &get() {
-        static Server s;
-        return s;
+        static Server *s = new Server();
+        return *s;
     }
 
     int configure(int64_t budget, int slots) {
         std::lock_guard<std::mutex> g(mu_);
         if (budget > 0)
             budget_ = budget;
-        if (slots > 0)
-            want_slots_ = slots;
+        if (slots > 0) {
+            if ((int)workers_ > slots)
+                return PHICOMB_EINVAL;   // slots can grow, not shrink
+            slots_ = slots;
+        }
         return PHICOMB_OK;
     }
 
@@ -58,7 +67,10 @@ class Server {
         std::unique_lock<std::mutex> g(mu_);
         if (req->bytes > budget_)
             return PHICOMB_EADMIT;
-        start_workers_locked();
+        while (workers_ < slots_) {
+            ++workers_;
+            std::thread([this]() { run(); }).detach();
+        }
         queue_.push_back(req);
         cv_.notify_all();
         return PHICOMB_OK;
@@ -75,16 +87,8 @@ class Server {
         hipGetDevice(&device_);
     }
 
-    void start_workers_locked() {
-        while ((int)workers_.size() < want_slots_) {
-            workers_.emplace_back(new Worker());
-            Worker *w = workers_.back();
-            w->th = std::thread([this, w]() { run(w); });
-            w->th.detach();
-        }
-    }
-
-    // First request in arrival order whose footprint fits the free budget.
+    // First request in arrival order whose footprint fits the free budget:
+    // a large request waiting for memory does not hold back smaller ones.
     phicomb_req take_locked() {
         for (auto it = queue_.begin(); it != queue_.end(); ++it) {
             if (in_use_ + (*it)->bytes <= budget_) {
@@ -97,32 +101,39 @@ class Server {
         return nullptr;
     }
 
-    void run(Worker *w) {
+    void run() {
+        Worker w;
         hipSetDevice(device_);
-        hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
-        hipHostMalloc((void **)&w->pinned, 64 * sizeof(double), hipHostMallocDefault);
+        const bool ok =
+            hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) == hipSuccess &&
+            hipHostMalloc((void **)&w.pinned, 64 * sizeof(double), hipHostMallocDefault) ==
+                hipSuccess;
         for (;;) {
             phicomb_req q = nullptr;
+            int floor_g = 1;
             {
                 std::unique_lock<std::mutex> g(mu_);
                 cv_.wait(g, [&]() { return (q = take_locked()) != nullptr; });
+                // every running solve is guaranteed a 1/slots share of the CUs
+                floor_g = std::max(1, device_cus(device_) / std::max(1, slots_));
             }
             q->state.store(1);
+            int st = ok ? PHICOMB_OK : PHICOMB_EDEVICE;
             const size_t need = solve_workspace_bytes(q->op->dev.n, q->p, q->r, q->precision);
-            int st = PHICOMB_OK;
-            if (w->ws_bytes < need) {
-                if (w->ws)
-                    hipFree(w->ws);
-                w->ws = nullptr;
-                w->ws_bytes = 0;
-                if (hipMalloc(&w->ws, need) != hipSuccess)
+            if (st == PHICOMB_OK && w.ws_bytes < need) {
+                if (w.ws)
+                    hipFree(w.ws);
+                w.ws = nullptr;
+                w.ws_bytes = 0;
+                if (hipMalloc(&w.ws, need) != hipSuccess)
                     st = PHICOMB_ENOMEM;
                 else
-                    w->ws_bytes = need;
+                    w.ws_bytes = need;
             }
             if (st == PHICOMB_OK)
-                st = solve_fp64(q->op, &q->prm, q->p, q->r, q->t, q->beta, q->V, q->tol, q->W,
-                                w->stream, &q->stats, w->ws, w->ws_bytes, w->pinned);
+                st = solve_run(q->op, &q->prm, q->p, q->r, q->t, q->beta, q->V, q->tol,
+                               q->precision, q->W, w.stream, &q->stats, w.ws, w.ws_bytes,
+                               w.pinned, floor_g);
             q->stats.status = st;
             q->status = st;
             {
@@ -137,9 +148,9 @@ class Server {
     std::mutex mu_;
     std::condition_variable cv_;
     std::deque<phicomb_req> queue_;
-    std::vector<Worker *> workers_;
+    int workers_ = 0;
     int64_t budget_ = 0, in_use_ = 0;
-    int want_slots_ = 4;
+    int slots_ = 4;
     int device_ = 0;
 };
 
@@ -175,9 +186,16 @@ int phicomb_submit(phicomb_op op, const phicomb_params_t *prm, int p, int r, con
         return PHICOMB_EINVAL;
     if (!(tol > 0.0) || !std::isfinite(tol) || prm->status != PHICOMB_OK)
         return PHICOMB_EINVAL;
+    if (!std::isfinite(prm->shift) || !std::isfinite(prm->s) || prm->s < 0.0)
+        return PHICOMB_EINVAL;
     if (!finite_array(t, r) || !finite_array(beta, (int64_t)r * (p + 1)))
         return PHICOMB_EINVAL;
     if (precision != PHICOMB_FP64 && precision != PHICOMB_MIXED)
+        return PHICOMB_EINVAL;
+    double tmax = 0.0;
+    for (int i = 0; i < r; ++i)
+        tmax = std::max(tmax, std::fabs(t[i]));
+    if (!(std::ceil(prm->s * tmax) <= 2147483647.0))
         return PHICOMB_EINVAL;
     phicomb_req q = new (std::nothrow) phicomb_req_s();
     if (!q)

@@ -48,6 +48,9 @@ struct SolveArgs {
     const double *V;                    // [n][p+1] row-major (caller)
     double *W;                          // [n][r]  row-major (caller)
     double *S, *U0, *U1, *E;
+    float *Uf0, *Uf1;                   // FP32 recovery term blocks [cR][n] (mixed precision)
+    double mix_tau;                     // tol / (10 u_fp32): FP32 term threshold
+    double mix_lo, mix_hi;              // partial-sum norms for which FP32 terms are safe
     unsigned *bar;                      // sync area (kSyncBytes)
     double *part;                       // [2][kMaxGrid][2] partial maxima
     int *info;                          // status, terms_S, terms_rec, max_terms_step
@@ -94,7 +97,18 @@ __device__ __forceinline__ void for_rows(int64_t lo, int64_t hi, F &&f) {
     }
 }
 
-template <int KIND, int R, int RPT, bool EMEM>
+// Mixed precision (MIX): in the recovery steps after the first, a Taylor
+// term is computed and stored in FP32 once the previous term is small enough
+// that FP32 rounding of the new one stays below tol/10 of the step's result
+// (an FP64 head then an FP32 tail).  The reference for "the step's result" is
+// the smaller of the partial sum and the step's starting block: partial sums
+// of a rough block swell through cancellation before they settle, so they
+// alone would let FP32 in too early.  The S-series and the first recovery
+// step (whose input carries the rough components of V) stay FP64, as do the
+// partial sums, the stopping test and everything carried across steps.
+constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predecessor
+
+template <int KIND, int R, int RPT, bool EMEM, bool MIX>
 __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
     __shared__ double Mk[kRMax][kPMax1][kPMax1];   // J_step^(k-1) / k!
     __shared__ double Cj[kRMax][kPMax1][kPMax1];   // gam[i][b] * Mk[i][b][.]
@@ -123,12 +137,14 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
         else
             return Ereg[decltype(q)::value][c];
     };
+    int n32 = 0;   // terms evaluated in FP32
     auto finish = [&](int st, int tS, int tR, int mS) {
         if (blockIdx.x == 0 && tid == 0) {
             P.info[0] = st;
             P.info[1] = tS;
             P.info[2] = tR;
             P.info[3] = mS;
+            P.info[4] = n32;
         }
     };
 
@@ -140,14 +156,18 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             load_cached_row(A, row, crow[decltype(q)::value]);
         });
-    auto opr = [&](int64_t row, auto q, const double *X, int col0, double shift,
+    auto opr = [&](int64_t row, auto q, const auto *X, int col0, double shift,
                    auto &y) __attribute__((always_inline)) {
-        constexpr int NC = std::extent<std::remove_reference_t<decltype(y)>>::value;
+        using Y = std::remove_reference_t<decltype(y)>;
+        constexpr int NC = std::extent<Y>::value;
+        using TA = std::remove_extent_t<Y>;
+        using TX = std::remove_cv_t<std::remove_pointer_t<decltype(X)>>;
         if constexpr (CACHED) {
-            apply_cached<NC>(crow[decltype(q)::value], (unsigned)row, X, n, col0, shift, y);
+            apply_cached<NC, TX, TA>(crow[decltype(q)::value], (unsigned)row, X, n, col0, shift,
+                                     y);
         } else {
             const RowCtx rc = row_ctx<KIND>(A, row);
-            apply_cols<KIND, NC>(A, rc, X, n, col0, shift, y);
+            apply_cols<KIND, NC, TX, TA>(A, rc, X, n, col0, shift, y);
         }
     };
 
@@ -337,28 +357,57 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
     for (int j = 1; j <= P.s_int - 1; ++j) {
         int kk = 0;
         double d1 = INFINITY, d2 = nF, nE = nF;
+        const double nF0 = nF;
+        bool in32 = false;   // the latest term is in Uf0/Uf1 (every step starts in FP64)
         while (d1 + d2 > P.tol * nE) {
             if (kk >= P.kcap) {
                 status = PHICOMB_ENOCONV;
                 break;
             }
             kk = kk + 1;
+            const double nref = fmin(nE, nF0);
+            const bool t32 =
+                MIX && (in32 || (j >= 2 && kk >= 2 && d2 * kMixSafety <= P.mix_tau * nref &&
+                                 nref >= P.mix_lo && nE <= P.mix_hi));
             d1 = d2;
             const double rk = 1.0 / (double)kk;
             const double *Fo = par ? P.U1 : P.U0;
             double *Fn = par ? P.U0 : P.U1;
+            const float *Fo32 = par ? P.Uf1 : P.Uf0;
+            float *Fn32 = par ? P.Uf0 : P.Uf1;
             double mx[2] = {0.0, 0.0};
             for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
-                double y[2 * R];
-                opr(row, q, Fo, 0, P.xi, y);
+                double f[2 * R];
+                if (MIX && in32) {
+                    float yf[2 * R];
+                    opr(row, q, Fo32, 0, P.xi, yf);
+#pragma unroll
+                    for (int c = 0; c < 2 * R; ++c) {
+                        const float ff = (yf[c] * (float)P.ts[c % R]) * (float)rk;
+                        Fn32[(int64_t)c * n + row] = ff;
+                        f[c] = (double)ff;
+                    }
+                } else {
+                    double y[2 * R];
+                    opr(row, q, Fo, 0, P.xi, y);
+#pragma unroll
+                    for (int c = 0; c < 2 * R; ++c) {
+                        f[c] = (y[c] * P.ts[c % R]) * rk;
+                        if (MIX && t32) {
+                            const float ff = (float)f[c];
+                            Fn32[(int64_t)c * n + row] = ff;
+                            f[c] = (double)ff;
+                        } else {
+                            Fn[(int64_t)c * n + row] = f[c];
+                        }
+                    }
+                }
                 double sf = 0.0, se = 0.0;
 #pragma unroll
                 for (int c = 0; c < 2 * R; ++c) {
-                    const double f = (y[c] * P.ts[c % R]) * rk;
                     double &e = Eref(row, q, c);
-                    e = e + f;
-                    Fn[(int64_t)c * n + row] = f;
-                    sf += fabs(f);
+                    e = e + f[c];
+                    sf += fabs(f[c]);
                     se += fabs(e);
                 }
                 mx[0] = nmax(mx[0], sf);
@@ -371,6 +420,8 @@ __global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
             d2 = mx[0];
             nE = mx[1];
             par ^= 1;
+            in32 = t32;
+            n32 += t32 ? 1 : 0;
         }
         if (!(d2 == d2) || !(nE == nE))
             status = PHICOMB_EDEVICE;
@@ -436,42 +487,44 @@ using KernelFn = void (*)(SolveArgs);
 
 // Instantiated variants: rows per thread 1..8 (register-cached CSR rows:
 // 1..4); larger counts spill and are served by the E-in-memory variant.
+// Mixed-precision variants exist for register-resident E with 1..4 rows per
+// thread; other shapes run the FP64 kernel (always at least as accurate).
 template <int KIND, int R>
-static KernelFn pick_rpt(int rpt, bool emem) {
+static KernelFn pick_rpt(int rpt, bool emem, bool mix) {
     if constexpr (KIND != kCsrCached) {
         if (emem)
-            return solve_kernel<KIND, R, 1, true>;
+            return mix ? nullptr : solve_kernel<KIND, R, 1, true, false>;
     }
     switch (rpt) {
-    case 1: return solve_kernel<KIND, R, 1, false>;
-    case 2: return solve_kernel<KIND, R, 2, false>;
-    case 4: return solve_kernel<KIND, R, 4, false>;
+    case 1: return mix ? solve_kernel<KIND, R, 1, false, true> : solve_kernel<KIND, R, 1, false, false>;
+    case 2: return mix ? solve_kernel<KIND, R, 2, false, true> : solve_kernel<KIND, R, 2, false, false>;
+    case 4: return mix ? solve_kernel<KIND, R, 4, false, true> : solve_kernel<KIND, R, 4, false, false>;
     case 8:
         if constexpr (KIND != kCsrCached)
-            return solve_kernel<KIND, R, 8, false>;
+            return mix ? nullptr : solve_kernel<KIND, R, 8, false, false>;
         return nullptr;
     default: return nullptr;
     }
 }
 
 template <int KIND>
-static KernelFn pick_r(int r, int rpt, bool emem) {
+static KernelFn pick_r(int r, int rpt, bool emem, bool mix) {
     switch (r) {
-    case 1: return pick_rpt<KIND, 1>(rpt, emem);
-    case 2: return pick_rpt<KIND, 2>(rpt, emem);
-    case 3: return pick_rpt<KIND, 3>(rpt, emem);
-    case 4: return pick_rpt<KIND, 4>(rpt, emem);
+    case 1: return pick_rpt<KIND, 1>(rpt, emem, mix);
+    case 2: return pick_rpt<KIND, 2>(rpt, emem, mix);
+    case 3: return pick_rpt<KIND, 3>(rpt, emem, mix);
+    case 4: return pick_rpt<KIND, 4>(rpt, emem, mix);
     default: return nullptr;
     }
 }
 
-static KernelFn pick_kernel(int kind, int r, int rpt, bool emem) {
+static KernelFn pick_kernel(int kind, int r, int rpt, bool emem, bool mix) {
     if (kind == kStencil)
-        return pick_r<kStencil>(r, rpt, emem);
+        return pick_r<kStencil>(r, rpt, emem, mix);
     if (kind == kCsr)
-        return pick_r<kCsr>(r, rpt, emem);
+        return pick_r<kCsr>(r, rpt, emem, mix);
     if (kind == kCsrCached && !emem)
-        return pick_r<kCsrCached>(r, rpt, false);
+        return pick_r<kCsrCached>(r, rpt, false, mix);
     return nullptr;
 }
 
@@ -496,17 +549,20 @@ static int max_coresident(KernelFn fn, int device) {
 
 static size_t sync_bytes() { return (size_t)kSyncBytes + sizeof(double) * 4 * kMaxGrid + 256; }
 
-size_t solve_workspace_bytes(int64_t n, int p, int r, int /*precision*/) {
+size_t solve_workspace_bytes(int64_t n, int p, int r, int precision) {
     const int64_t cS = (int64_t)(p + 1) * r, cR = 2LL * r, cW = std::max(cS, cR);
-    return sync_bytes() + (size_t)8 * (size_t)n * (size_t)(cS + 2 * cW + cR);
+    const size_t f32 = (precision == PHICOMB_MIXED) ? (size_t)4 * n * 2 * cR + 256 : 0;
+    return sync_bytes() + (size_t)8 * (size_t)n * (size_t)(cS + 2 * cW + cR) + f32;
 }
 
 // Algorithmic bytes of one solve (FP64): every Taylor term reads and writes
 // its term block and its partial-sum block; the S-series terms also read V;
 // the operator is read once per product (CSR arrays; stencil weights are
 // in registers).
+// Mixed precision: an FP32 term reads and writes its term block in 4-byte
+// words (8 n c bytes fewer per term).
 static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, int r,
-                                int terms_S, int terms_rec, int s_int) {
+                                int terms_S, int terms_rec, int s_int, int f32_rec) {
     const double w = 8.0, N = (double)n;
     const double cS = (double)(p + 1) * r, cR = 2.0 * r;
     const double opb = (op.kind == kCsr) ? (12.0 * (double)nnz + 4.0 * (N + 1)) : 0.0;
@@ -516,12 +572,51 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
     b += terms_rec * (4 * w * N * cR + opb);                            // recovery terms
     b += (s_int - 1) * (w * N * p * r + 2 * w * N * cR);                // step epilogues
     b += 3 * w * N * r;                                                 // combine
+    b -= 8.0 * N * f32_rec * cR;                                         // FP32 term blocks
     return b;
 }
 
-int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
-               const double *beta, const void *V, double tol, void *W, hipStream_t stream,
-               phicomb_stats_t *stats, void *ws, size_t ws_bytes, double *pinned) {
+// Variant choice within a budget of `cap` workgroups (at most one per CU:
+// the barrier cost grows with the number of workgroups): the fewest rows per
+// thread of {1, 2, 4, 8} that covers n with E in registers and no register
+// spills; a shape with no mixed kernel takes the FP64 one; otherwise E moves
+// to memory and rows are grid-strided.
+static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_needed1, int cap,
+                               int64_t *G) {
+    const int kind = (op->dev.kind == kCsr && op->dev.max_row_nnz <= kCacheNnz) ? kCsrCached
+                                                                                  : op->dev.kind;
+    for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
+        const bool m = mix && pass == 0;
+        for (int rpt : {1, 2, 4, 8}) {
+            KernelFn f = pick_kernel(kind, r, rpt, false, m);
+            if (!f)
+                continue;
+            hipFuncAttributes fa;
+            if (hipFuncGetAttributes(&fa, (const void *)f) != hipSuccess || fa.localSizeBytes > 0)
+                continue;
+            const int maxg = std::min(max_coresident(f, op->device), cap);
+            const int64_t g = (wgs_needed1 + rpt - 1) / rpt;
+            if (maxg >= 1 && g <= maxg) {
+                *G = g;
+                return f;
+            }
+        }
+    }
+    KernelFn f = pick_kernel(op->dev.kind, r, 1, true, false);
+    if (!f)
+        return nullptr;
+    const int maxg = std::min(max_coresident(f, op->device), cap);
+    if (maxg < 1)
+        return nullptr;
+    *G = std::min<int64_t>(maxg, wgs_needed1);
+    return f;
+}
+
+int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+              const double *beta, const void *V, double tol, int precision, void *W,
+              hipStream_t stream, phicomb_stats_t *stats, void *ws, size_t ws_bytes,
+              double *pinned, int cu_floor) {
+    const bool mix = (precision == PHICOMB_MIXED);
     const int64_t n = op->dev.n;
     const int P1 = p + 1;
     SolveArgs a;
@@ -572,50 +667,45 @@ int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const d
     a.U1 = d;
     d += (size_t)n * cW;
     a.E = d;
+    d += (size_t)n * a.cR;
+    if (mix) {
+        float *f = (float *)(((uintptr_t)d + 255) & ~(uintptr_t)255);
+        a.Uf0 = f;
+        a.Uf1 = f + (size_t)n * a.cR;
+    }
+    a.mix_tau = tol / (10.0 * 5.9604644775390625e-08);   // u_fp32 = 2^-24
+    // FP32 terms stay clear of overflow ((A - xi I) x with |x| <= partial sum)
+    // and of the subnormal range.
+    a.mix_lo = 1e-20;
+    a.mix_hi = 1e30 / std::max(1.0, op->norm_inf + std::fabs(prm->shift));
     a.V = (const double *)V;
     a.W = (double *)W;
-    if (solve_workspace_bytes(n, p, r, PHICOMB_FP64) > ws_bytes)
+    if (solve_workspace_bytes(n, p, r, precision) > ws_bytes)
         return PHICOMB_EINVAL;
 
-    // Variant choice: at most one workgroup per CU (the barrier cost grows
-    // with the number of workgroups), then the fewest rows per thread of
-    // {1, 2, 4, 8} that covers n with E in registers and no register
-    // spills; otherwise E moves to memory and rows are grid-strided.
-    KernelFn fn = nullptr;
-    int64_t G = 0;
     const int64_t wgs_needed1 = (n + kNT - 1) / kNT;
-    int cus = 256;
-    {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, op->device) == hipSuccess)
-            cus = prop.multiProcessorCount;
-    }
-    const int kind = (op->dev.kind == kCsr && op->dev.max_row_nnz <= kCacheNnz) ? kCsrCached
-                                                                                  : op->dev.kind;
-    for (int rpt : {1, 2, 4, 8}) {
-        KernelFn f = pick_kernel(kind, r, rpt, false);
-        if (!f)
-            continue;
-        hipFuncAttributes fa;
-        if (hipFuncGetAttributes(&fa, (const void *)f) != hipSuccess || fa.localSizeBytes > 0)
-            continue;
-        const int maxg = std::min(max_coresident(f, op->device), cus);
-        const int64_t g = (wgs_needed1 + rpt - 1) / rpt;
-        if (maxg >= 1 && g <= maxg) {
-            fn = f;
-            G = g;
-            break;
-        }
-    }
+    const int cus = device_cus(op->device);
+    // Persistent launches on one device draw workgroup slots from a shared
+    // ledger so that concurrent solves never exceed co-residency together.
+    const int want = (int)std::min<int64_t>(cus, wgs_needed1);
+    const int floor_g = (cu_floor > 0) ? std::min(want, cu_floor) : want;
+    const int granted = cu_acquire(op->device, want, floor_g);
+    if (granted < 1)
+        return PHICOMB_EDEVICE;
+    int64_t G = 0;
+    KernelFn fn = select_variant(op, r, mix, wgs_needed1, granted, &G);
     if (!fn) {
-        fn = pick_kernel(op->dev.kind, r, 1, true);
-        if (!fn)
-            return PHICOMB_EINVAL;
-        const int maxg = max_coresident(fn, op->device);
-        if (maxg < 1)
-            return PHICOMB_EDEVICE;
-        G = std::min<int64_t>(std::min(maxg, cus), wgs_needed1);
+        cu_release(op->device, granted);
+        return PHICOMB_EINVAL;
     }
+    // keep round_xcd(G) slots: at most ceil(G/8) of the grid lands on any XCD
+    const int held = std::min(granted, round_xcd(G));
+    if (held < granted)
+        cu_release(op->device, granted - held);
+    struct Hold {
+        int dev, g;
+        ~Hold() { cu_release(dev, g); }
+    } hold{op->device, held};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool timed = (hipEventCreate(&e0) == hipSuccess) && (hipEventCreate(&e1) == hipSuccess);
     solve_sync_init<<<1, 256, 0, stream>>>(a.bar, a.info);
@@ -643,8 +733,10 @@ int solve_fp64(phicomb_op op, const phicomb_params_t *prm, int p, int r, const d
         stats->terms_S = info[1];
         stats->terms_rec = info[2];
         stats->max_terms_step = info[3];
+        stats->fp32_terms = info[4];
         stats->status = st;
-        stats->bytes_alg = algorithmic_bytes(op->dev, op->nnz, n, p, r, info[1], info[2], s_int);
+        stats->bytes_alg = algorithmic_bytes(op->dev, op->nnz, n, p, r, info[1], info[2], s_int,
+                                             info[4]);
         float ms = 0.0f;
         if (timed && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
             stats->ms = ms;

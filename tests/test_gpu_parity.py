@@ -14,7 +14,7 @@ import pytest
 import oracle
 import refs
 import workloads as wl
-from gpu_util import gpu_solve, say
+from gpu_util import gpu_solve, load_golden, sampled_err, say
 
 import paper_2509_26475_amd as pc
 
@@ -116,6 +116,25 @@ def test_config3_full_size_against_dst(tol):
     err = refs.rel2_cols(Wg, exact)
     say(f"      s_int={sg['s_int']} terms {sg['terms_S']}/{sg['terms_rec']} err={err.max():.2e}")
     assert err.max() <= max(10 * tol, 1e-12)
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-12])
+def test_config3_nonnormal_full_size_sampled(tol):
+    pr = wl.config3(nonnormal=True, tol=tol)
+    g = load_golden(tol)
+    say(f"[gpu] {pr.name} full n={pr.n} tol={tol:g} (sampled oracle rows)")
+    Wg, sg, _ = gpu_solve(pr, prm=g["params"])
+    err = sampled_err(Wg, g)
+    so = g["stats"]
+    say(f"      s_int={sg['s_int']} terms S {so['terms_S']}/{sg['terms_S']} "
+        f"rec {so['terms_rec']}/{sg['terms_rec']} sampled err {np.array2string(err, precision=2)}")
+    assert sg["s_int"] == so["s_int"]
+    assert abs(sg["terms_S"] - so["terms_S"]) <= 1
+    assert abs(sg["terms_rec"] - so["terms_rec"]) <= max(1, so["s_int"] // 4)
+    assert err.max() <= TOL_FP64
+    # the column norms of the full result agree as well
+    cn = np.linalg.norm(Wg, axis=0)
+    assert np.allclose(cn, g["col_norm2"], rtol=TOL_FP64, atol=0)
 
 
 # --------------------------------------------------------------- edge cases
