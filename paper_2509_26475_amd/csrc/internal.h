@@ -73,8 +73,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // (workgroup release) and arrives at its group counter; the last arrival of a
 // group (the leader) writes the XCD's L2 back and arrives at the top counter;
 // the last leader opens the top generation; each leader then invalidates its
-// XCD's L2 and opens its group's generation; members invalidate their CU's L1
-// and continue.  Members cannot write between their leader's write-back and
+// caches and opens its group's generation; members invalidate theirs (agent
+// scope, which includes the CU's L1) and continue.  Members cannot write between their leader's write-back and
 // invalidate, so no dirty line is dropped.  Every wait is bounded; a timeout
 // returns false and the kernel reports PHICOMB_EDEVICE.
 constexpr int kLineU = 64;              // uint32 per 256-byte line
@@ -107,18 +107,19 @@ __device__ __forceinline__ bool spin_until_ne(const unsigned *p, unsigned v) {
     return true;
 }
 
-// Agent-scope release and acquire of this XCD's L2, each waited for in the
-// same asm block: the compiler's own fences can emit the write-back without
-// a wait for its completion, and a counter update that overtakes the
-// write-back lets another XCD read this XCD's stale lines.  The acquire also
-// invalidates the CU's vector L1 explicitly: without it a leader's CU kept
-// lines of the buffer it had read two barriers earlier (same parity of the
-// double-buffered terms and partials) and read them back stale.
+// Agent-scope release and acquire, each waited for in the same asm block:
+// the compiler's own fences can emit the write-back without a wait for its
+// completion, and a counter update that overtakes the write-back lets
+// another XCD read stale lines.  The acquire (buffer_inv at agent scope,
+// sc1) also invalidates the CU's vector L1; every workgroup needs it after a
+// barrier.  A workgroup-scope invalidate (sc0) leaves the L1 alone: lines of
+// a double-buffered block read two barriers earlier then come back stale
+// once the per-term traffic is small enough not to evict them.
 __device__ __forceinline__ void l2_writeback() {
     __asm__ volatile("buffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
 }
 __device__ __forceinline__ void l2_invalidate() {
-    __asm__ volatile("buffer_inv sc1\n\tbuffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    __asm__ volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
 }
 
 // Every wave waits until its own global stores are acknowledged by the L2
@@ -189,8 +190,7 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
         } else {
             if (!spin_until_ne(gg, g))
                 ok = 0;
-            // invalidate this CU's vector L1 (the leader invalidated the L2)
-            __asm__ volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+            l2_invalidate();   // this CU's L1 (and non-coherent L2 lines)
         }
         gs.gen = g + 1;
         *ok_lds = ok;

@@ -487,13 +487,13 @@ using KernelFn = void (*)(SolveArgs);
 
 // Instantiated variants: rows per thread 1..8 (register-cached CSR rows:
 // 1..4); larger counts spill and are served by the E-in-memory variant.
-// Mixed-precision variants exist for register-resident E with 1..4 rows per
-// thread; other shapes run the FP64 kernel (always at least as accurate).
+// Mixed-precision variants exist for E in registers with 1..4 rows per
+// thread and for E in memory; other shapes run the FP64 kernel.
 template <int KIND, int R>
 static KernelFn pick_rpt(int rpt, bool emem, bool mix) {
     if constexpr (KIND != kCsrCached) {
         if (emem)
-            return mix ? nullptr : solve_kernel<KIND, R, 1, true, false>;
+            return mix ? solve_kernel<KIND, R, 1, true, true> : solve_kernel<KIND, R, 1, true, false>;
     }
     switch (rpt) {
     case 1: return mix ? solve_kernel<KIND, R, 1, false, true> : solve_kernel<KIND, R, 1, false, false>;
@@ -580,7 +580,10 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
 // the barrier cost grows with the number of workgroups): the fewest rows per
 // thread of {1, 2, 4, 8} that covers n with E in registers and no register
 // spills; a shape with no mixed kernel takes the FP64 one; otherwise E moves
-// to memory and rows are grid-strided.
+// to memory and rows are grid-strided.  Some instantiations carry a small
+// private frame with no scratch traffic in their code (up to kFrameOk
+// bytes); spilling ones have hundreds.
+constexpr size_t kFrameOk = 64;
 static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_needed1, int cap,
                                int64_t *G) {
     const int kind = (op->dev.kind == kCsr && op->dev.max_row_nnz <= kCacheNnz) ? kCsrCached
@@ -592,7 +595,8 @@ static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_neede
             if (!f)
                 continue;
             hipFuncAttributes fa;
-            if (hipFuncGetAttributes(&fa, (const void *)f) != hipSuccess || fa.localSizeBytes > 0)
+            if (hipFuncGetAttributes(&fa, (const void *)f) != hipSuccess ||
+                fa.localSizeBytes > kFrameOk)
                 continue;
             const int maxg = std::min(max_coresident(f, op->device), cap);
             const int64_t g = (wgs_needed1 + rpt - 1) / rpt;
@@ -602,7 +606,7 @@ static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_neede
             }
         }
     }
-    KernelFn f = pick_kernel(op->dev.kind, r, 1, true, false);
+    KernelFn f = pick_kernel(op->dev.kind, r, 1, true, mix);
     if (!f)
         return nullptr;
     const int maxg = std::min(max_coresident(f, op->device), cap);
