@@ -68,6 +68,104 @@ def cpu_baseline(problem) -> dict:
                       f"single-threaded C, {dt:.2f} s"}
 
 
+def _norm_inf(op) -> float:
+    """max_i sum_j |a_ij| of an operator description (interior stencil row)."""
+    if op.kind == "stencil":
+        k = 5 if op.dim == 2 else 7
+        return float(abs(op.coef[:k]).sum() + abs(op.superdiag))
+    import numpy as np
+    return float(np.abs(op.A).sum(axis=1).max())
+
+
+def bench_mixed(pc, wl, torch, reps: int) -> list:
+    """Solves/s of FP64 and mixed precision on the 128^3 Laplacian and its
+    nonnormal variant at tol 1e-6 (parameters computed once per operator)."""
+    out = []
+    for nonnormal in (False, True):
+        pr = wl.config3(nonnormal=nonnormal, tol=1e-6)
+        op = pc.Operator(pr.op)
+        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
+        V = torch.from_numpy(pr.V).cuda()
+        W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
+        row = {"workload": pr.name + "_p2_r2_tol1e-6"}
+        for name, prec in (("fp64", pc.FP64), ("mixed", pc.MIXED)):
+            pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, prec, W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = [pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, prec, W)
+                   for _ in range(reps)]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            st = sts[-1]
+            row[name + "_solves_per_s"] = 1.0 / dt
+            row[name + "_kernel_ms"] = st.ms
+            if prec == pc.MIXED:
+                row["fp32_term_fraction"] = st.fp32_terms / max(1, st.terms_S + st.terms_rec)
+        row["mixed_over_fp64"] = row["mixed_solves_per_s"] / row["fp64_solves_per_s"]
+        out.append(row)
+        op.close()
+    return out
+
+
+def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
+    """Poisson request stream over a resident operator pool (70 % 2-D/3-D
+    stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
+    p ~ U{1..4}, r ~ U{1..3}, tol 1e-6 (mixed; dense FP64) or 1e-10 (FP64).
+    Latency = completion seen by polling - scheduled arrival."""
+    import numpy as np
+    ops, reqs = wl.config5_stream(duration_s=duration, rate=rate)
+    handles = [pc.Operator(o) for o in ops]
+    norms = [_norm_inf(o) for o in ops]
+    prms = {}
+    for i, h in enumerate(handles):
+        for tol in (1e-6, 1e-10):
+            prms[(i, tol)] = pc.phicomb_params(h.h, tol, 61, None, 1)
+    pc.phicomb_serve_config(0, slots)
+    gen = torch.Generator(device="cuda")
+    lat, pending, kernel_ms = [], [], []
+    i, n_done = 0, 0
+    t0 = time.perf_counter()
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i]["arrival"] <= now:
+            q = reqs[i]
+            op = ops[q["op_index"]]
+            p, r = q["p"], q["r"]
+            t = (np.arange(1, r + 1) / r) * q["gamma"] / norms[q["op_index"]]
+            gen.manual_seed(q["seed"])
+            V = torch.randn((op.n, p + 1), generator=gen, dtype=torch.float64, device="cuda")
+            W = torch.empty((op.n, r), dtype=torch.float64, device="cuda")
+            torch.cuda.current_stream().synchronize()
+            prec = pc.MIXED if (q["tol"] == 1e-6 and op.kind != "dense") else pc.FP64
+            tk = pc.phicomb_submit(handles[q["op_index"]].h, prms[(q["op_index"], q["tol"])],
+                                   p, r, t, np.ones((r, p + 1)), V, q["tol"], prec, W)
+            pending.append((tk, q["arrival"], V, W))
+            i += 1
+        still = []
+        for tk, arr, V, W in pending:
+            st, stats = pc.phicomb_poll(tk)
+            if st == pc.PENDING:
+                still.append((tk, arr, V, W))
+                continue
+            if st != pc.OK:
+                raise RuntimeError(f"served request failed: {pc.phicomb_strerror(st)}")
+            lat.append(time.perf_counter() - t0 - arr)
+            kernel_ms.append(stats.ms)
+            n_done += 1
+        pending = still
+        if pending or i < len(reqs):
+            time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    for h in handles:
+        h.close()
+    lat_ms = 1e3 * np.asarray(lat)
+    return {"workload": f"poisson {rate:g}/s x {duration:g} s, 64 stencil + 32 dense ops",
+            "requests": n_done, "slots": slots, "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
+            "throughput_req_per_s": n_done / wall,
+            "mean_kernel_ms": float(np.mean(kernel_ms))}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +173,11 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kind", choices=["csr", "stencil"], default="csr")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision and served-stream measurements")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args(argv)
@@ -159,12 +262,17 @@ def main(argv=None) -> int:
         "terms_rec": stats[-1]["terms_rec"],
         "shift": prm.shift, "s": prm.s,
     }
+    op.close()
+    if not args.no_extras:
+        line["mixed_tol1e-6"] = bench_mixed(pc, wl, torch, reps=5)
+        if args.serve_seconds > 0:
+            line["served"] = bench_served(pc, wl, torch, args.serve_seconds, args.serve_rate,
+                                          args.serve_slots)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pr)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
-    op.close()
     return 0
 
 
