@@ -190,6 +190,51 @@ int phicomb_serve_config(int64_t budget_bytes, int slots);
 /* Device footprint in bytes of one request (V, W and work blocks). */
 int64_t phicomb_request_bytes(int64_t n, int p, int r, int precision);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent solves (Sec. 4, Algorithm 3 each) of uneven size in one
+ * persistent launch.  The library splits the launch into groups of
+ * workgroups, each running an ordered list of the instances, with group sizes
+ * and lists chosen from a cost model of one Taylor term and the expected term
+ * count of every instance (s_int steps of the length tol implies), so that
+ * the predicted finishing time of the last group is smallest.  The launch is
+ * captured once into a HIP graph and replayed by every run.
+ *   items     [count] solves: same fields as phicomb_solve; every operator of
+ *             the kind stencil or CSR (dense operators are CSR inside), all of
+ *             one kind and on the current device.  t and beta are copied at
+ *             create; V and W are device pointers kept by the plan: their
+ *             contents may change between runs, the pointers may not.
+ *   count     1..PHICOMB_MAX_BATCH.
+ * The plan holds its own work blocks (sum of solve_workspace sizes).
+ * Errors: EINVAL (bad item, mixed kinds or devices), ENOMEM, EDEVICE. */
+#define PHICOMB_MAX_BATCH 4096
+
+typedef struct phicomb_batch_s *phicomb_batch;
+
+typedef struct {
+    phicomb_op op;
+    const phicomb_params_t *prm;
+    int32_t p, r;
+    const double *t;     /* host [r] */
+    const double *beta;  /* host [r][p+1] */
+    const void *V;       /* device [n][p+1] row-major */
+    void *W;             /* device [n][r] row-major, written by runs */
+    double tol;
+} phicomb_batch_item;
+
+int phicomb_batch_create(int count, const phicomb_batch_item *items, int precision,
+                         phicomb_batch *out);
+
+/* Runs every solve of the plan on stream (blocking).  stats: optional
+ * [count]; ms is the duration of the whole launch.  Returns OK or the first
+ * failing instance's status (every instance still runs). */
+int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats);
+
+/* The plan's schedule: number of groups, workgroups of the launch, and the
+ * cost model's predicted duration (milliseconds). */
+int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *predicted_ms);
+
+int phicomb_batch_destroy(phicomb_batch b);
+
 const char *phicomb_strerror(int status);
 
 #ifdef __cplusplus

@@ -53,6 +53,12 @@ class StatsT(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchItemT(C.Structure):
+    _fields_ = [("op", C.c_void_p), ("prm", C.POINTER(ParamsT)), ("p", C.c_int32),
+                ("r", C.c_int32), ("t", C.c_void_p), ("beta", C.c_void_p), ("V", C.c_void_p),
+                ("W", C.c_void_p), ("tol", C.c_double)]
+
+
 _LIB = None
 
 
@@ -78,6 +84,10 @@ def _lib():
             "phicomb_serve_config": ([I64, I32], I32),
             "phicomb_request_bytes": ([I64, I32, I32, I32], I64),
             "phicomb_strerror": ([I32], C.c_char_p),
+            "phicomb_batch_create": ([I32, P, I32, P], I32),
+            "phicomb_batch_run": ([P, P, P], I32),
+            "phicomb_batch_info": ([P, P, P, P], I32),
+            "phicomb_batch_destroy": ([P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -200,6 +210,47 @@ def phicomb_request_bytes(n: int, p: int, r: int, precision: int = FP64) -> int:
 
 def phicomb_strerror(status: int) -> str:
     return _lib().phicomb_strerror(status).decode()
+
+
+def phicomb_batch_create(items, precision: int = FP64):
+    """items: sequence of (op_handle, ParamsT, p, r, t, beta, V, W, tol) with V, W
+    float64 CUDA tensors ([n][p+1], [n][r]).  Returns the plan handle."""
+    keep = []
+    arr = (BatchItemT * len(items))()
+    for k, (h, prm, p, r, t, beta, V, W, tol) in enumerate(items):
+        ta = np.ascontiguousarray(t, dtype=np.float64)
+        ba = np.ascontiguousarray(beta, dtype=np.float64)
+        _check_device_tensor(V, (None, p + 1), "V")
+        _check_device_tensor(W, (None, r), "W")
+        keep += [ta, ba, prm]
+        arr[k].op = h.value if isinstance(h, C.c_void_p) else h
+        arr[k].prm = C.pointer(prm)
+        arr[k].p, arr[k].r = int(p), int(r)
+        arr[k].t, arr[k].beta = ta.ctypes.data, ba.ctypes.data
+        arr[k].V, arr[k].W = V.data_ptr(), W.data_ptr()
+        arr[k].tol = float(tol)
+    out = C.c_void_p()
+    _check(_lib().phicomb_batch_create(len(items), arr, int(precision), C.byref(out)),
+           "phicomb_batch_create")
+    return out
+
+
+def phicomb_batch_run(b, count: int, stream=None):
+    """Runs the plan; returns (status, [StatsT] * count)."""
+    stats = (StatsT * count)()
+    st = _lib().phicomb_batch_run(b, _stream_ptr(stream), stats)
+    return st, list(stats)
+
+
+def phicomb_batch_info(b) -> dict:
+    g, w, ms = C.c_int(), C.c_int(), C.c_double()
+    _check(_lib().phicomb_batch_info(b, C.byref(g), C.byref(w), C.byref(ms)),
+           "phicomb_batch_info")
+    return {"groups": g.value, "workgroups": w.value, "predicted_ms": ms.value}
+
+
+def phicomb_batch_destroy(b) -> None:
+    _check(_lib().phicomb_batch_destroy(b), "phicomb_batch_destroy")
 
 
 def _check_device_tensor(x, shape, name):

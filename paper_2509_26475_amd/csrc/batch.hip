@@ -1,0 +1,562 @@
+// Batched solves: many Algorithm 3 instances (Sec. 4) of uneven size in one
+// persistent launch.
+//
+// The launch is split into groups of workgroups.  Each group runs an ordered
+// list of instances one after the other, every instance on the group's whole
+// sub-grid with its own barrier area and work blocks, so groups never wait
+// for each other.  The host picks the group sizes and lists from a cost model
+// of one Taylor term (barrier latency plus the term's bytes over the group's
+// CUs) and the expected term count of each instance (s_int steps of the
+// Taylor length that tol implies), minimising the predicted makespan: an
+// instance that alone needs more than the makespan gets a group of several
+// workgroups, the rest are packed longest-first onto single workgroups.
+// The launch (barrier reset and solve kernel) is captured once into a HIP
+// graph and replayed by every run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "solve_body.h"
+
+using namespace phc;
+
+namespace phc {
+
+// Variant of an instance inside the batched kernel: R (1..4) and the row
+// layout (1, 2 or 4 rows per thread with E in registers, or E in memory).
+constexpr int kLayouts = 4;
+constexpr int kLayoutEmem = 3;
+
+// Resets every instance's barrier area and status words (one block each).
+__global__ void batch_sync_init(const SolveArgs *__restrict__ args, int count) {
+    const int it = blockIdx.x;
+    if (it >= count)
+        return;
+    unsigned *bar = args[it].bar;
+    for (int i = threadIdx.x; i < kSyncLines * kLineU; i += blockDim.x)
+        bar[i] = 0u;
+    if (threadIdx.x < 8)
+        args[it].info[threadIdx.x] = 0;
+}
+
+template <int KIND, int R, bool MIX>
+__device__ __forceinline__ void run_layout(int layout, const SolveArgs &P, SolveShared &sh,
+                                           unsigned G, unsigned bid) {
+    switch (layout) {
+    case 0: solve_body<KIND, R, 1, false, MIX>(P, sh, G, bid, (int)bid); break;
+    case 1: solve_body<KIND, R, 2, false, MIX>(P, sh, G, bid, (int)bid); break;
+    case 2: solve_body<KIND, R, 4, false, MIX>(P, sh, G, bid, (int)bid); break;
+    default: solve_body<KIND, R, 1, true, MIX>(P, sh, G, bid, (int)bid); break;
+    }
+}
+
+// wg_group[b]: group of workgroup b; gfirst/gsize: first workgroup and size of
+// each group; glist[goff[g] .. goff[g+1]): the instances group g runs, in order.
+template <int KIND, bool MIX>
+__global__ __launch_bounds__(kNT) void solve_batch_kernel(const SolveArgs *__restrict__ args,
+                                                          const int *__restrict__ variant,
+                                                          const int *__restrict__ wg_group,
+                                                          const int *__restrict__ gfirst,
+                                                          const int *__restrict__ gsize,
+                                                          const int *__restrict__ goff,
+                                                          const int *__restrict__ glist) {
+    __shared__ SolveShared sh;
+    const int g = wg_group[blockIdx.x];
+    const unsigned G = (unsigned)gsize[g];
+    const unsigned bid = blockIdx.x - (unsigned)gfirst[g];
+    for (int q = goff[g]; q < goff[g + 1]; ++q) {
+        const int it = glist[q];
+        const SolveArgs &P = args[it];
+        const int v = variant[it];
+        const int layout = v % kLayouts;
+        switch (v / kLayouts) {
+        case 0: run_layout<KIND, 1, MIX>(layout, P, sh, G, bid); break;
+        case 1: run_layout<KIND, 2, MIX>(layout, P, sh, G, bid); break;
+        case 2: run_layout<KIND, 3, MIX>(layout, P, sh, G, bid); break;
+        default: run_layout<KIND, 4, MIX>(layout, P, sh, G, bid); break;
+        }
+        __syncthreads();   // the next instance reuses the shared state
+    }
+}
+
+using BatchKernel = void (*)(const SolveArgs *, const int *, const int *, const int *,
+                             const int *, const int *, const int *);
+
+static BatchKernel pick_batch_kernel(int kind, bool mix) {
+    if (kind == kStencil)
+        return mix ? solve_batch_kernel<kStencil, true> : solve_batch_kernel<kStencil, false>;
+    if (kind == kCsr)
+        return mix ? solve_batch_kernel<kCsr, true> : solve_batch_kernel<kCsr, false>;
+    return nullptr;
+}
+
+// ------------------------------------------------------------ cost model
+// Terms of one Taylor loop at tolerance tol: the scaled step has norm about
+// theta = (tol m!)^(1/m) (m = 61, Sec. 3), and the loop runs until
+// theta^k / k! drops below tol.
+static double taylor_terms(double tol) {
+    const double m = 61.0;
+    const double lt = std::log(std::max(tol, 1e-300));
+    const double theta = std::exp((lt + std::lgamma(m + 1.0)) / m);
+    const double lth = std::log(theta);
+    int k = 1;
+    while (k < kTermCap && (k * lth - std::lgamma(k + 1.0)) > lt)
+        ++k;
+    return (double)k + 1.0;
+}
+
+struct ItemCost {
+    double terms;   // Taylor terms over the whole solve
+    double bytes;   // bytes of one term
+    int64_t n;
+    int gmax;       // most workgroups that still own 512 rows each
+};
+
+// One term on G workgroups, microseconds: barrier plus the term's bytes at
+// a per-CU streaming rate.
+static double term_us(const ItemCost &c, int G) {
+    const double barrier = (G == 1) ? 1.5 : 3.0 + 0.006 * G;
+    return barrier + c.bytes / ((double)G * 25e3);
+}
+static double cost_us(const ItemCost &c, int G) { return c.terms * term_us(c, G); }
+
+struct Schedule {
+    std::vector<int> gsize;                 // per group
+    std::vector<std::vector<int>> glist;    // per group, instance order
+    double makespan = 0.0;
+    int wgs = 0;
+};
+
+// Smallest predicted makespan M with a schedule of at most cap workgroups:
+// every instance gets the fewest workgroups that finish it within M; those
+// needing one are packed longest-first onto single workgroups (first fit).
+static bool schedule_for(const std::vector<ItemCost> &c, int cap, double M, Schedule &out) {
+    const int count = (int)c.size();
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(),
+              [&](int a, int b) { return cost_us(c[a], 1) > cost_us(c[b], 1); });
+    Schedule s;
+    std::vector<double> load;   // single-workgroup groups
+    std::vector<int> single_group;
+    for (int it : order) {
+        int G = 1;
+        while (G < c[it].gmax && cost_us(c[it], G) > M)
+            ++G;
+        if (cost_us(c[it], G) > M && G == c[it].gmax && G > 1) {
+            // cannot meet M even with every useful workgroup
+            return false;
+        }
+        if (G > 1) {
+            s.gsize.push_back(G);
+            s.glist.push_back({it});
+            s.wgs += G;
+            continue;
+        }
+        const double t = cost_us(c[it], 1);
+        int best = -1;
+        for (size_t k = 0; k < load.size(); ++k)
+            if (load[k] + t <= M) {
+                best = (int)k;
+                break;
+            }
+        if (best < 0) {
+            if (t > M)
+                return false;
+            load.push_back(0.0);
+            s.gsize.push_back(1);
+            s.glist.push_back({});
+            single_group.push_back((int)s.gsize.size() - 1);
+            s.wgs += 1;
+            best = (int)load.size() - 1;
+        }
+        load[best] += t;
+        s.glist[single_group[best]].push_back(it);
+        if (s.wgs > cap)
+            return false;
+    }
+    if (s.wgs > cap)
+        return false;
+    double mk = 0.0;
+    for (size_t g = 0; g < s.gsize.size(); ++g) {
+        double t = 0.0;
+        for (int it : s.glist[g])
+            t += cost_us(c[it], s.gsize[g]);
+        mk = std::max(mk, t);
+    }
+    s.makespan = mk;
+    out = std::move(s);
+    return true;
+}
+
+static Schedule make_schedule(const std::vector<ItemCost> &c, int cap) {
+    double lo = 0.0, hi = 0.0;
+    for (const auto &x : c)
+        hi += cost_us(x, 1);
+    hi = std::max(hi, 1.0);
+    Schedule best;
+    if (!schedule_for(c, cap, hi, best)) {
+        // more instances than workgroups with everything on one: one group per
+        // workgroup, instances dealt longest-first
+        best = Schedule();
+        const int ng = std::min<int>(cap, (int)c.size());
+        best.gsize.assign(ng, 1);
+        best.glist.assign(ng, {});
+        std::vector<double> load(ng, 0.0);
+        std::vector<int> order(c.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(),
+                  [&](int a, int b) { return cost_us(c[a], 1) > cost_us(c[b], 1); });
+        for (int it : order) {
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[k] += cost_us(c[it], 1);
+            best.glist[k].push_back(it);
+        }
+        best.wgs = ng;
+        best.makespan = *std::max_element(load.begin(), load.end());
+        return best;
+    }
+    for (int iter = 0; iter < 60; ++iter) {
+        const double mid = 0.5 * (lo + hi);
+        Schedule s;
+        if (schedule_for(c, cap, mid, s)) {
+            best = std::move(s);
+            hi = mid;
+        } else {
+            lo = mid;
+        }
+        if (hi - lo < 1e-3 * hi)
+            break;
+    }
+    return best;
+}
+
+}  // namespace phc
+
+struct phicomb_batch_s {
+    int device = 0;
+    int count = 0;
+    int kind = 0;
+    bool mix = false;
+    std::vector<phicomb_op> ops;
+    std::vector<int> p, r, s_int;
+    Schedule sched;
+    int wgs = 0;
+    void *mem = nullptr;          // device: args, tables, status words, work blocks
+    SolveArgs *args = nullptr;
+    int *tables = nullptr;        // variant, wg_group, gfirst, gsize, goff, glist
+    int ng = 0;
+    int *info_dev = nullptr;      // [count][8], gathered after the solve
+    int *info_host = nullptr;     // pinned copy
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchKernel kernel = nullptr;
+};
+
+namespace {
+
+__global__ void batch_gather_info(const SolveArgs *__restrict__ args, int *__restrict__ out,
+                                  int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count * 8)
+        out[i] = args[i / 8].info[i % 8];
+}
+
+void free_batch(phicomb_batch b) {
+    if (!b)
+        return;
+    if (b->exec)
+        hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        hipGraphDestroy(b->graph);
+    if (b->cap_stream)
+        hipStreamDestroy(b->cap_stream);
+    if (b->mem)
+        hipFree(b->mem);
+    if (b->info_host)
+        hipHostFree(b->info_host);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int phicomb_batch_create(int count, const phicomb_batch_item *items, int precision,
+                         phicomb_batch *out) {
+    if (!out || !items || count < 1 || count > PHICOMB_MAX_BATCH)
+        return PHICOMB_EINVAL;
+    *out = nullptr;
+    if (precision != PHICOMB_FP64 && precision != PHICOMB_MIXED)
+        return PHICOMB_EINVAL;
+    phicomb_batch b = new (std::nothrow) phicomb_batch_s();
+    if (!b)
+        return PHICOMB_ENOMEM;
+    b->count = count;
+    b->mix = (precision == PHICOMB_MIXED);
+    int st = PHICOMB_OK;
+    // validation and per-instance shapes
+    for (int i = 0; i < count && st == PHICOMB_OK; ++i) {
+        const phicomb_batch_item &q = items[i];
+        if (!q.op || !q.prm || !q.t || !q.beta || !q.V || !q.W || q.p < 0 ||
+            q.p > PHICOMB_MAX_P || q.r < 1 || q.r > PHICOMB_MAX_R || !(q.tol > 0.0) ||
+            !std::isfinite(q.tol) || q.prm->status != PHICOMB_OK || !std::isfinite(q.prm->s) ||
+            !std::isfinite(q.prm->shift) || q.prm->s < 0.0)
+            st = PHICOMB_EINVAL;
+        for (int k = 0; st == PHICOMB_OK && k < q.r; ++k)
+            if (!std::isfinite(q.t[k]))
+                st = PHICOMB_EINVAL;
+        for (int k = 0; st == PHICOMB_OK && k < q.r * (q.p + 1); ++k)
+            if (!std::isfinite(q.beta[k]))
+                st = PHICOMB_EINVAL;
+        if (st != PHICOMB_OK)
+            break;
+        const int kind = q.op->dev.kind;
+        if (i == 0) {
+            b->kind = kind;
+            b->device = q.op->device;
+        } else if (kind != b->kind || q.op->device != b->device) {
+            st = PHICOMB_EINVAL;   // one operator kind and device per batch
+        }
+    }
+    if (st == PHICOMB_OK && !(b->kernel = pick_batch_kernel(b->kind, b->mix)))
+        st = PHICOMB_EINVAL;
+    if (st != PHICOMB_OK) {
+        free_batch(b);
+        return st;
+    }
+    // workspace sizes and cost model
+    std::vector<size_t> ws(count);
+    std::vector<ItemCost> cost(count);
+    const size_t sync_b = solve_sync_bytes();
+    size_t work_total = 0;
+    for (int i = 0; i < count; ++i) {
+        const phicomb_batch_item &q = items[i];
+        const int64_t n = q.op->dev.n;
+        ws[i] = (solve_workspace_bytes(n, q.p, q.r, precision) + 255) & ~(size_t)255;
+        work_total += ws[i];
+        double tmax = 0.0;
+        for (int k = 0; k < q.r; ++k)
+            tmax = std::max(tmax, std::fabs(q.t[k]));
+        const double sc = std::ceil(q.prm->s * tmax);
+        if (!(sc <= 2147483647.0)) {
+            free_batch(b);
+            return PHICOMB_EINVAL;
+        }
+        const double steps = std::max(1.0, sc);
+        const double k = taylor_terms(q.tol);
+        const double opb = (q.op->dev.kind == kCsr) ? 12.0 * q.op->nnz / (double)n : 0.0;
+        cost[i].terms = k * steps;
+        cost[i].bytes = (double)n * (24.0 * 2 * q.r + opb);
+        cost[i].n = n;
+        cost[i].gmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + kNT - 1) / kNT));
+    }
+    const int cap = device_cus(b->device) / kXcds * kXcds;
+    b->sched = make_schedule(cost, cap);
+    b->wgs = b->sched.wgs;
+    const int ng = (int)b->sched.gsize.size();
+    // device memory: args | variant | wg_group | gfirst | gsize | goff | glist | info | work
+    const size_t args_b = sizeof(SolveArgs) * count;
+    const size_t ntab = (size_t)count + b->wgs + 3 * (size_t)ng + 1 + count;
+    const size_t tab_b = (sizeof(int) * ntab + 255) & ~(size_t)255;
+    const size_t info_b = (sizeof(int) * 8 * count + 255) & ~(size_t)255;
+    const size_t args_pad = (args_b + 255) & ~(size_t)255;
+    (void)sync_b;
+    const size_t total = args_pad + tab_b + info_b + work_total;
+    if (hipSetDevice(b->device) != hipSuccess || hipMalloc(&b->mem, total) != hipSuccess ||
+        hipHostMalloc((void **)&b->info_host, sizeof(int) * 8 * count, hipHostMallocDefault) !=
+            hipSuccess) {
+        free_batch(b);
+        return PHICOMB_ENOMEM;
+    }
+    char *base = (char *)b->mem;
+    b->args = (SolveArgs *)base;
+    b->tables = (int *)(base + args_pad);
+    b->info_dev = (int *)(base + args_pad + tab_b);
+    char *work = base + args_pad + tab_b + info_b;
+    std::vector<SolveArgs> args(count);
+    std::vector<int> variant(count), group_of(count, 0);
+    for (int g = 0; g < ng; ++g)
+        for (int it : b->sched.glist[g])
+            group_of[it] = g;
+    size_t off = 0;
+    b->ops.resize(count);
+    b->p.resize(count);
+    b->r.resize(count);
+    b->s_int.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const phicomb_batch_item &q = items[i];
+        st = build_solve_args(q.op, q.prm, q.p, q.r, q.t, q.beta, q.V, q.tol, precision, q.W,
+                              work + off, ws[i], args[i]);
+        if (st != PHICOMB_OK) {
+            free_batch(b);
+            return st;
+        }
+        off += ws[i];
+        const int G = b->sched.gsize[group_of[i]];
+        const int64_t rows_per_thread = (q.op->dev.n + (int64_t)kNT * G - 1) / ((int64_t)kNT * G);
+        const int layout = rows_per_thread <= 1 ? 0
+                           : rows_per_thread <= 2 ? 1
+                           : rows_per_thread <= 4 ? 2
+                                                   : kLayoutEmem;
+        variant[i] = (q.r - 1) * kLayouts + layout;
+        b->ops[i] = q.op;
+        b->p[i] = q.p;
+        b->r[i] = q.r;
+        b->s_int[i] = args[i].s_int;
+    }
+    // tables
+    std::vector<int> tab(ntab);
+    int *t_variant = tab.data();
+    int *t_wg = t_variant + count;
+    int *t_gfirst = t_wg + b->wgs;
+    int *t_gsize = t_gfirst + ng;
+    int *t_goff = t_gsize + ng;
+    int *t_glist = t_goff + ng + 1;
+    std::copy(variant.begin(), variant.end(), t_variant);
+    int wg = 0, lo = 0;
+    for (int g = 0; g < ng; ++g) {
+        t_gfirst[g] = wg;
+        t_gsize[g] = b->sched.gsize[g];
+        for (int k = 0; k < b->sched.gsize[g]; ++k)
+            t_wg[wg++] = g;
+        t_goff[g] = lo;
+        for (int it : b->sched.glist[g])
+            t_glist[lo++] = it;
+    }
+    t_goff[ng] = lo;
+    if (hipMemcpy(b->args, args.data(), args_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->tables, tab.data(), sizeof(int) * ntab, hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        free_batch(b);
+        return PHICOMB_EDEVICE;
+    }
+    b->ng = ng;
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        free_batch(b);
+        return PHICOMB_EDEVICE;
+    }
+    *out = b;
+    return PHICOMB_OK;
+}
+
+static hipError_t enqueue_batch(phicomb_batch b, hipStream_t s) {
+    const int count = b->count, ng = b->ng;
+    const int *t_variant = b->tables;
+    const int *t_wg = t_variant + count;
+    const int *t_gfirst = t_wg + b->wgs;
+    const int *t_gsize = t_gfirst + ng;
+    const int *t_goff = t_gsize + ng;
+    const int *t_glist = t_goff + ng + 1;
+    batch_sync_init<<<count, 256, 0, s>>>(b->args, count);
+    const SolveArgs *a = b->args;
+    void *kargs[] = {(void *)&a,      (void *)&t_variant, (void *)&t_wg,   (void *)&t_gfirst,
+                     (void *)&t_gsize, (void *)&t_goff,    (void *)&t_glist};
+    hipError_t e = hipLaunchKernel((const void *)b->kernel, dim3(b->wgs), dim3(kNT), kargs, 0, s);
+    if (e != hipSuccess)
+        return e;
+    batch_gather_info<<<(count * 8 + 255) / 256, 256, 0, s>>>(b->args, b->info_dev, count);
+    return hipMemcpyAsync(b->info_host, b->info_dev, sizeof(int) * 8 * count,
+                          hipMemcpyDeviceToHost, s);
+}
+
+int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats) {
+    if (!b)
+        return PHICOMB_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return PHICOMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // the launch is captured once; a failed capture falls back to direct launches
+    if (!b->exec && !b->graph) {
+        bool ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) ==
+                  hipSuccess;
+        if (ok) {
+            const hipError_t e = enqueue_batch(b, b->cap_stream);
+            hipGraph_t g = nullptr;
+            ok = (hipStreamEndCapture(b->cap_stream, &g) == hipSuccess) && e == hipSuccess;
+            if (ok && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                b->graph = g;
+            } else {
+                if (g)
+                    hipGraphDestroy(g);
+                b->exec = nullptr;
+                hipGetLastError();
+            }
+        }
+        if (!b->exec)
+            b->graph = (hipGraph_t)1;   // remember: no graph on this runtime
+    }
+    const int held = round_xcd(b->wgs);
+    if (cu_acquire(b->device, held, held) != held)
+        return PHICOMB_EDEVICE;
+    struct Hold {
+        int dev, g;
+        ~Hold() { cu_release(dev, g); }
+    } hold{b->device, held};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (timed)
+        hipEventRecord(e0, s);
+    const hipError_t le = b->exec ? hipGraphLaunch(b->exec, s) : enqueue_batch(b, s);
+    if (timed)
+        hipEventRecord(e1, s);
+    const bool synced = (le == hipSuccess) && hipStreamSynchronize(s) == hipSuccess;
+    float ms = 0.0f;
+    if (timed) {
+        if (synced)
+            hipEventElapsedTime(&ms, e0, e1);
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+    }
+    if (!synced)
+        return PHICOMB_EDEVICE;
+    int worst = PHICOMB_OK;
+    for (int i = 0; i < b->count; ++i) {
+        const int *info = b->info_host + 8 * i;
+        if (info[0] != PHICOMB_OK && worst == PHICOMB_OK)
+            worst = info[0];
+        if (stats) {
+            phicomb_stats_t &o = stats[i];
+            std::memset(&o, 0, sizeof(o));
+            o.s_int = b->s_int[i];
+            o.terms_S = info[1];
+            o.terms_rec = info[2];
+            o.max_terms_step = info[3];
+            o.fp32_terms = info[4];
+            o.status = info[0];
+            o.bytes_alg = solve_algorithmic_bytes(b->ops[i], b->p[i], b->r[i], b->s_int[i], info);
+            o.ms = ms;
+        }
+    }
+    return worst;
+}
+
+int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *predicted_ms) {
+    if (!b)
+        return PHICOMB_EINVAL;
+    if (groups)
+        *groups = b->ng;
+    if (workgroups)
+        *workgroups = b->wgs;
+    if (predicted_ms)
+        *predicted_ms = b->sched.makespan * 1e-3;
+    return PHICOMB_OK;
+}
+
+int phicomb_batch_destroy(phicomb_batch b) {
+    if (!b)
+        return PHICOMB_EINVAL;
+    if (b->graph == (hipGraph_t)1)
+        b->graph = nullptr;
+    free_batch(b);
+    return PHICOMB_OK;
+}
+
+}  // extern "C"

@@ -128,7 +128,8 @@ __device__ __forceinline__ void l2_invalidate() {
 __device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
 // One-time flat, fully fenced registration barrier; thread 0 fills gs.
-__device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_lds) {
+__device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_lds,
+                                           unsigned nblocks) {
     wait_own_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -137,7 +138,7 @@ __device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_
         atomicAdd(bar + kLineU * (kLnGroupSize + x), 1u);
         l2_writeback();
         const unsigned prev = atomicAdd(bar + kLineU * kLnSetup, 1u);
-        if (prev == gridDim.x - 1) {
+        if (prev == nblocks - 1) {
             l2_writeback();
             __hip_atomic_store(bar + kLineU * kLnSetupFlag, 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -199,10 +200,11 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
     return *ok_lds != 0;
 }
 
-// Workgroup max of NV values into part[blockIdx.x*2 + j] (plain stores,
-// published by the next grid_sync).
+// Workgroup max of NV values into part[bid*2 + j] (plain stores, published by
+// the next grid_sync); bid is the workgroup's index within its grid.
 template <int NV, int NT>
-__device__ __forceinline__ void store_partials(double (&v)[NV], double *part, double (*red)[2]) {
+__device__ __forceinline__ void store_partials(double (&v)[NV], double *part, double (*red)[2],
+                                               unsigned bid) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
@@ -220,7 +222,7 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double *part, do
             double m = red[0][j];
             for (int w = 1; w < NT / 64; ++w)
                 m = nmax(m, red[w][j]);
-            part[blockIdx.x * 2 + j] = m;
+            part[bid * 2 + j] = m;
         }
     }
 }

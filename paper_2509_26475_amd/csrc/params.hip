@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     };
 
     GridSync gs;
-    if (!grid_setup(gs, P.bar, &ok_lds)) {
+    if (!grid_setup(gs, P.bar, &ok_lds, gridDim.x)) {
         finish(PHICOMB_EDEVICE, 0, 0, 0, 0, 0, 0, 0);
         return;
     }

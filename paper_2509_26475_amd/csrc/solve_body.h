@@ -1,0 +1,501 @@
+// Device side of the Algorithm 3 solve, shared by the single-solve kernel
+// (solve.hip) and the batched kernel (batch.hip).
+// Block truncated-Taylor scaling-and-recovering solve (Al-Mohy, Sec. 4,
+// Algorithm 3; r = 1 is Algorithm 2), FP64, one persistent cooperative kernel.
+//
+// Work blocks are column-major ([columns][n]) so that every column access of
+// a wave64 is one contiguous 512-byte segment:
+//   S  [(p+1) r][n]  scaled block series S of (rec.D); column (b, i) at b*r + i,
+//                    block b holding v_perm(b), perm = (0, p, p-1, ..., 1)
+//   U0, U1           ping-pong term blocks: D_k/k! in the S-series, then the
+//                    Taylor terms F of the recovery loop (2r columns); they are
+//                    the only blocks other workgroups read (operator products)
+//   E                partial sums of the recovery loop: registers of the
+//                    thread that owns the row (rows per thread fixed at compile
+//                    time), or [2r][n] in memory for very large n
+// The weights beta are folded into the columns of V (Corollary of Theorem 1),
+// so the Kronecker factor J (x) Delta reduces to one J per abscissa and
+// exp(J (x) Delta / s) to exp(J/s).  The replicated V of the listing is never
+// stored: its k-th update V J_step^(k-1) is formed per row from the p+1 input
+// vectors with (p+1)^2 coefficients per abscissa kept in LDS.
+//
+// Every Taylor term ends with one grid-wide exchange: each workgroup writes
+// the maxima of its row sums (block infinity norms), crosses the XCD-grouped
+// grid barrier, and reduces all workgroups' maxima itself, so every thread
+// takes the same stopping decision.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <utility>
+
+#include "internal.h"
+
+namespace phc {
+
+constexpr int kNT = 512;           // threads per workgroup of the solve kernel (8 waves)
+constexpr int kMaxGrid = 4096;     // partial-maximum slots per parity
+
+struct SolveArgs {
+    DevOp op;
+    int64_t n;
+    int p, r, P1, cS, cR, s_int, kcap;
+    double tol, xi, nu;                 // nu = 1/s_int (superdiagonal of the J step)
+    double ts[kRMax];                   // t_i / s_int
+    double t[kRMax];                    // t_i
+    double mu[kRMax];                   // exp(xi t_i / s_int): undo factor of the shift
+    double w0[kRMax];                   // beta_i0: weight of v_0 in exp(t_i A/s) v_0
+    double a[kRMax];                    // -xi t_i / s_int: diagonal of the J step
+    double gam[kRMax][kPMax1];          // column (b,i) scale beta_{i,perm(b)} mu_i / s_int
+    const double *V;                    // [n][p+1] row-major (caller)
+    double *W;                          // [n][r]  row-major (caller)
+    double *S, *U0, *U1, *E;
+    float *Uf0, *Uf1;                   // FP32 recovery term blocks [cR][n] (mixed precision)
+    double mix_tau;                     // tol / (10 u_fp32): FP32 term threshold
+    double mix_lo, mix_hi;              // partial-sum norms for which FP32 terms are safe
+    unsigned *bar;                      // sync area (kSyncBytes)
+    double *part;                       // [2][kMaxGrid][2] partial maxima
+    int *info;                          // status, terms_S, terms_rec, max_terms_step
+};
+
+template <class F, int... Q>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Q...>) {
+    (f(std::integral_constant<int, Q>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Visit the rows this thread owns.  Register-resident layout: RPT rows at
+// stride kNT inside the workgroup's contiguous chunk, visited with a
+// compile-time index q; memory layout: a grid-stride loop over the chunk.
+template <int RPT, bool EMEM, class F>
+__device__ __forceinline__ void for_rows(int64_t lo, int64_t hi, F &&f) {
+    if constexpr (EMEM) {
+        for (int64_t row = lo + threadIdx.x; row < hi; row += kNT)
+            f(row, std::integral_constant<int, 0>{});
+    } else {
+        static_for<RPT>([&](auto q) {
+            unsigned r32 = (unsigned)(lo + threadIdx.x) + (unsigned)(decltype(q)::value * kNT);
+            // opaque to the optimiser: addresses derived from the row are
+            // rebuilt inside every Taylor term instead of being hoisted out
+            // of the term loop and kept live for all RPT rows
+            __asm__ volatile("" : "+v"(r32));
+            const int64_t row = (int64_t)r32;
+            if (row < hi)
+                f(row, q);
+            // keep the rows apart: their loads would otherwise be interleaved
+            // and multiply the register footprint by RPT
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+}
+
+// Mixed precision (MIX): in the recovery steps after the first, a Taylor
+// term is computed and stored in FP32 once the previous term is small enough
+// that FP32 rounding of the new one stays below tol/10 of the step's result
+// (an FP64 head then an FP32 tail).  The reference for "the step's result" is
+// the smaller of the partial sum and the step's starting block: partial sums
+// of a rough block swell through cancellation before they settle, so they
+// alone would let FP32 in too early.  The S-series and the first recovery
+// step (whose input carries the rough components of V) stay FP64, as do the
+// partial sums, the stopping test and everything carried across steps.
+constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predecessor
+
+// Workgroup-shared state of one solve.
+struct SolveShared {
+    double Mk[kRMax][kPMax1][kPMax1];   // J_step^(k-1) / k!
+    double Cj[kRMax][kPMax1][kPMax1];   // gam[i][b] * Mk[i][b][.]
+    double red[kNT / 64][2];
+    int ok;
+};
+
+// Algorithm 3 for one solve on a grid of G workgroups; this workgroup is
+// number bid of them and owns the rows of logical block lb.
+template <int KIND, int R, int RPT, bool EMEM, bool MIX>
+__device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, const unsigned G,
+                                           const unsigned bid, const int lb) {
+    auto &Mk = sh.Mk;
+    auto &Cj = sh.Cj;
+    auto &red = sh.red;
+    const int64_t n = P.n;
+    int64_t lo, hi;
+    if constexpr (EMEM) {
+        const int64_t chunk = (n + G - 1) / G;
+        lo = std::min<int64_t>(n, (int64_t)lb * chunk);
+        hi = std::min<int64_t>(n, lo + chunk);
+    } else {
+        lo = std::min<int64_t>(n, (int64_t)lb * kNT * RPT);
+        hi = std::min<int64_t>(n, lo + (int64_t)kNT * RPT);
+    }
+    const int tid = threadIdx.x;
+    const int P1 = P.P1, p = P.p;
+    const DevOp &A = P.op;
+    double Ereg[EMEM ? 1 : RPT][2 * R];
+    auto Eref = [&](int64_t row, auto q, int c) -> double & {
+        if constexpr (EMEM)
+            return P.E[(int64_t)c * n + row];
+        else
+            return Ereg[decltype(q)::value][c];
+    };
+    int n32 = 0;   // terms evaluated in FP32
+    auto finish = [&](int st, int tS, int tR, int mS) {
+        if (bid == 0 && tid == 0) {
+            P.info[0] = st;
+            P.info[1] = tS;
+            P.info[2] = tR;
+            P.info[3] = mS;
+            P.info[4] = n32;
+        }
+    };
+
+    // Operator rows: CSR rows of at most kCacheNnz entries stay in registers
+    // for the whole solve; other kinds rebuild their row context per product.
+    constexpr bool CACHED = (KIND == kCsrCached);
+    CachedRow crow[CACHED ? RPT : 1];
+    if constexpr (CACHED)
+        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+            load_cached_row(A, row, crow[decltype(q)::value]);
+        });
+    auto opr = [&](int64_t row, auto q, const auto *X, int col0, double shift,
+                   auto &y) __attribute__((always_inline)) {
+        using Y = std::remove_reference_t<decltype(y)>;
+        constexpr int NC = std::extent<Y>::value;
+        using TA = std::remove_extent_t<Y>;
+        using TX = std::remove_cv_t<std::remove_pointer_t<decltype(X)>>;
+        if constexpr (CACHED) {
+            apply_cached<NC, TX, TA>(crow[decltype(q)::value], (unsigned)row, X, n, col0, shift,
+                                     y);
+        } else {
+            const RowCtx rc = row_ctx<KIND>(A, row);
+            apply_cols<KIND, NC, TX, TA>(A, rc, X, n, col0, shift, y);
+        }
+    };
+
+    GridSync gs;
+    if (!grid_setup(gs, P.bar, &sh.ok, G)) {
+        finish(PHICOMB_EDEVICE, 0, 0, 0);
+        return;
+    }
+    unsigned epoch = 0;
+    // publish this workgroup's maxima, cross the barrier, reduce all of them
+    auto exchange = [&](auto &v) __attribute__((always_inline)) -> bool {
+        constexpr int NV = std::extent<std::remove_reference_t<decltype(v)>>::value;
+        double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
+        store_partials<NV, kNT>(v, pt, red, bid);
+        if (!grid_sync(gs, &sh.ok))
+            return false;
+        load_partials<NV, kNT>(pt, G, v, red);
+        ++epoch;
+        return true;
+    };
+
+    // ---- S = D = V (I (x) 1^T mu/s), beta-prescaled; M_1 = I
+    if (tid < R * kPMax1 * kPMax1) {
+        const int i = tid / (kPMax1 * kPMax1), b = (tid / kPMax1) % kPMax1, c = tid % kPMax1;
+        Mk[i][b][c] = (b == c) ? 1.0 : 0.0;
+    }
+    double nrm[2] = {0.0, 0.0};
+    for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto) {
+        double su = 0.0;
+        for (int b = 0; b < P1; ++b) {
+            const int pb = (b == 0) ? 0 : p + 1 - b;
+            const double vv = P.V[row * P1 + pb];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const double u = vv * P.gam[i][b];
+                const int64_t o = (int64_t)(b * R + i) * n + row;
+                P.U0[o] = u;
+                P.S[o] = u;
+                su += fabs(u);
+            }
+        }
+        nrm[0] = nmax(nrm[0], su);
+    });
+    nrm[1] = nrm[0];
+    if (!exchange(nrm)) {
+        finish(PHICOMB_EDEVICE, 0, 0, 0);
+        return;
+    }
+    double c2 = nrm[0], nS = nrm[1];
+
+    // ---- S-series (rec.D) with the stopping test (stopTm) after every term
+    int status = PHICOMB_OK;
+    int k = 1;
+    double c1 = INFINITY;
+    int par = 0;   // the latest term lives in U0 (par = 0) or U1
+    while (c1 + c2 > P.tol * nS) {
+        if (k >= P.kcap) {
+            status = PHICOMB_ENOCONV;
+            break;
+        }
+        k = k + 1;
+        c1 = c2;
+        const double rk = 1.0 / (double)k;
+        // M_k = M_{k-1} J_step / k with J_step = a_i I + nu J  (J: ones on
+        // (b, b+1) for 1 <= b < p); C = gam * M_k.
+        {
+            const bool act = tid < R * P1 * P1;
+            int i = 0, b = 0, c = 0;
+            double nv = 0.0;
+            if (act) {
+                i = tid / (P1 * P1);
+                b = (tid / P1) % P1;
+                c = tid % P1;
+                nv = (Mk[i][b][c] * P.a[i] + (c >= 2 ? Mk[i][b][c - 1] * P.nu : 0.0)) * rk;
+            }
+            __syncthreads();
+            if (act) {
+                Mk[i][b][c] = nv;
+                Cj[i][b][c] = P.gam[i][b] * nv;
+            }
+            __syncthreads();
+        }
+        const double *Uo = par ? P.U1 : P.U0;
+        double *Un = par ? P.U0 : P.U1;
+        double mx[2] = {0.0, 0.0};
+        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+            double vr[kPMax1];   // reordered v: vr[b] = v_perm(b)(row)
+#pragma unroll
+            for (int b = 0; b < kPMax1; ++b)
+                vr[b] = (b < P1) ? P.V[row * P1 + ((b == 0) ? 0 : p + 1 - b)] : 0.0;
+            double su = 0.0, ss = 0.0;
+#pragma unroll 1
+            for (int b = 0; b < P1; ++b) {
+                double y[R];
+                opr(row, q, Uo, b * R, P.xi, y);
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    double jt;
+                    if (b == 0) {
+                        jt = Cj[i][0][0] * vr[0];   // block 0 couples to itself only
+                    } else {
+                        jt = 0.0;
+#pragma unroll
+                        for (int bb = 1; bb < kPMax1; ++bb)
+                            if (bb <= b)
+                                jt += Cj[i][bb][b] * vr[bb];
+                    }
+                    const double u = (y[i] * P.ts[i]) * rk + jt;
+                    const int64_t o = (int64_t)(b * R + i) * n + row;
+                    Un[o] = u;
+                    const double s = P.S[o] + u;
+                    P.S[o] = s;
+                    su += fabs(u);
+                    ss += fabs(s);
+                }
+            }
+            mx[0] = nmax(mx[0], su);
+            mx[1] = nmax(mx[1], ss);
+        });
+        if (!exchange(mx)) {
+            finish(PHICOMB_EDEVICE, k, 0, 0);
+            return;
+        }
+        c2 = mx[0];
+        nS = mx[1];
+        par ^= 1;
+    }
+    if (!(c2 == c2) || !(nS == nS))
+        status = PHICOMB_EDEVICE;
+    const int terms_S = k;
+    if (status != PHICOMB_OK) {
+        finish(status, terms_S, 0, 0);
+        return;
+    }
+
+    // ---- F = [S_0, S_p];  F_1 <- A F_1 T + beta_0 v_0  (recovers exp(t_i A/s) v_0)
+    const bool one_step = (P.s_int == 1);
+    double nF = 0.0;
+    {
+        double mx[1] = {0.0};
+        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+            double y[R];
+            opr(row, q, P.S, 0, 0.0, y);
+            const double v0 = P.V[row * P1];
+            double f1[R], f2[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                f1[i] = y[i] * P.t[i] + P.w0[i] * v0;
+                f2[i] = (p >= 1) ? P.S[(int64_t)(p * R + i) * n + row] : 0.0;
+            }
+            if (one_step) {
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    P.W[row * R + i] = f1[i] + f2[i];
+            } else {
+                double sf = 0.0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    P.U0[(int64_t)i * n + row] = f1[i];
+                    Eref(row, q, i) = f1[i];
+                    sf += fabs(f1[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    P.U0[(int64_t)(R + i) * n + row] = f2[i];
+                    Eref(row, q, R + i) = f2[i];
+                    sf += fabs(f2[i]);
+                }
+                mx[0] = nmax(mx[0], sf);
+            }
+        });
+        if (one_step) {
+            finish(PHICOMB_OK, terms_S, 0, 0);
+            return;
+        }
+        if (!exchange(mx)) {
+            finish(PHICOMB_EDEVICE, terms_S, 0, 0);
+            return;
+        }
+        nF = mx[0];
+    }
+
+    // ---- recovery (rec.F.shift): s-1 steps of exp(t(A - xi I)/s), each ended by
+    //      E <- E mu, F_2 <- E_2 + (S exp(jJ/s))_p, F_1 <- E_1
+    int tot = 0, maxstep = 0;
+    par = 0;   // current F in U0
+    for (int j = 1; j <= P.s_int - 1; ++j) {
+        int kk = 0;
+        double d1 = INFINITY, d2 = nF, nE = nF;
+        const double nF0 = nF;
+        bool in32 = false;   // the latest term is in Uf0/Uf1 (every step starts in FP64)
+        while (d1 + d2 > P.tol * nE) {
+            if (kk >= P.kcap) {
+                status = PHICOMB_ENOCONV;
+                break;
+            }
+            kk = kk + 1;
+            const double nref = fmin(nE, nF0);
+            const bool t32 =
+                MIX && (in32 || (j >= 2 && kk >= 2 && d2 * kMixSafety <= P.mix_tau * nref &&
+                                 nref >= P.mix_lo && nE <= P.mix_hi));
+            d1 = d2;
+            const double rk = 1.0 / (double)kk;
+            const double *Fo = par ? P.U1 : P.U0;
+            double *Fn = par ? P.U0 : P.U1;
+            const float *Fo32 = par ? P.Uf1 : P.Uf0;
+            float *Fn32 = par ? P.Uf0 : P.Uf1;
+            double mx[2] = {0.0, 0.0};
+            for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+                double f[2 * R];
+                if (MIX && in32) {
+                    float yf[2 * R];
+                    opr(row, q, Fo32, 0, P.xi, yf);
+#pragma unroll
+                    for (int c = 0; c < 2 * R; ++c) {
+                        const float ff = (yf[c] * (float)P.ts[c % R]) * (float)rk;
+                        Fn32[(int64_t)c * n + row] = ff;
+                        f[c] = (double)ff;
+                    }
+                } else {
+                    double y[2 * R];
+                    opr(row, q, Fo, 0, P.xi, y);
+#pragma unroll
+                    for (int c = 0; c < 2 * R; ++c) {
+                        f[c] = (y[c] * P.ts[c % R]) * rk;
+                        if (MIX && t32) {
+                            const float ff = (float)f[c];
+                            Fn32[(int64_t)c * n + row] = ff;
+                            f[c] = (double)ff;
+                        } else {
+                            Fn[(int64_t)c * n + row] = f[c];
+                        }
+                    }
+                }
+                double sf = 0.0, se = 0.0;
+#pragma unroll
+                for (int c = 0; c < 2 * R; ++c) {
+                    double &e = Eref(row, q, c);
+                    e = e + f[c];
+                    sf += fabs(f[c]);
+                    se += fabs(e);
+                }
+                mx[0] = nmax(mx[0], sf);
+                mx[1] = nmax(mx[1], se);
+            });
+            if (!exchange(mx)) {
+                finish(PHICOMB_EDEVICE, terms_S, tot + kk, maxstep);
+                return;
+            }
+            d2 = mx[0];
+            nE = mx[1];
+            par ^= 1;
+            in32 = t32;
+            n32 += t32 ? 1 : 0;
+        }
+        if (!(d2 == d2) || !(nE == nE))
+            status = PHICOMB_EDEVICE;
+        tot += kk;
+        maxstep = std::max(maxstep, kk);
+        if (status != PHICOMB_OK) {
+            finish(status, terms_S, tot, maxstep);
+            return;
+        }
+        // (exp(jJ/s))_{b,p} = (j/s)^(p-b)/(p-b)!, b >= 1
+        double cd[kPMax1];
+        cd[0] = 1.0;
+#pragma unroll
+        for (int d = 1; d < kPMax1; ++d)
+            cd[d] = cd[d - 1] * ((double)j * P.nu) / (double)d;
+        const bool last = (j == P.s_int - 1);
+        double *Fx = par ? P.U1 : P.U0;   // overwrite the latest term: only E is needed
+        double mx[1] = {0.0};
+        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+            double f1[R], f2[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                f1[i] = Eref(row, q, i) * P.mu[i];
+                double acc = Eref(row, q, R + i) * P.mu[i];
+                for (int b = 1; b <= p; ++b)
+                    acc += P.S[(int64_t)(b * R + i) * n + row] * cd[p - b];
+                f2[i] = acc;
+            }
+            if (last) {
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    P.W[row * R + i] = f1[i] + f2[i];
+            } else {
+                double sf = 0.0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    Fx[(int64_t)i * n + row] = f1[i];
+                    Eref(row, q, i) = f1[i];
+                    sf += fabs(f1[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    Fx[(int64_t)(R + i) * n + row] = f2[i];
+                    Eref(row, q, R + i) = f2[i];
+                    sf += fabs(f2[i]);
+                }
+                mx[0] = nmax(mx[0], sf);
+            }
+        });
+        if (last)
+            break;
+        if (!exchange(mx)) {
+            finish(PHICOMB_EDEVICE, terms_S, tot, maxstep);
+            return;
+        }
+        nF = mx[0];
+    }
+    finish(status, terms_S, tot, maxstep);
+}
+
+// ---------------------------------------------------------------- host side
+// (implemented in solve.hip)
+size_t solve_sync_bytes();
+// Fills every field of a for one solve; the workspace ws (solve_workspace_bytes
+// for this shape and precision) receives the sync area and the work blocks.
+// Returns PHICOMB_OK, or PHICOMB_EINVAL when ceil(s max|t|) exceeds INT_MAX or
+// the workspace is too small.
+int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+                     const double *beta, const void *V, double tol, int precision, void *W,
+                     void *ws, size_t ws_bytes, SolveArgs &a);
+// Algorithmic bytes of a finished solve (info as written by the kernel).
+double solve_algorithmic_bytes(phicomb_op op, int p, int r, int s_int, const int *info);
+
+}  // namespace phc
