@@ -107,6 +107,43 @@ def bench_mixed(pc, wl, torch, reps: int) -> list:
     return out
 
 
+def bench_batched(pc, wl, torch, reps: int) -> dict:
+    """256 kappa-Laplacians of uneven size (side U{32..256}, kappa
+    logU[1e-2, 1e2], p, r U{1,2,3}, t logU[1e-5, 1e-2], tol 1e-8) in one
+    persistent launch (graph replay), FP32 bulk (mixed) and FP64."""
+    probs = wl.config4()
+    ops = [pc.Operator(pr.op) for pr in probs]
+    prms = [pc.phicomb_params(o.h, pr.tol, 61, None, 1) for o, pr in zip(ops, probs)]
+    Vd = [torch.from_numpy(pr.V).cuda() for pr in probs]
+    Wd = [torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda") for pr in probs]
+    items = [(ops[k].h, prms[k], pr.p, pr.r, pr.t, pr.beta, Vd[k], Wd[k], pr.tol)
+             for k, pr in enumerate(probs)]
+    torch.cuda.synchronize()
+    out = {"workload": "256 kappa-Laplacians 2-D, side U{32..256}, p,r U{1,2,3}, tol 1e-8",
+           "instances": len(probs)}
+    for name, prec in (("mixed", pc.MIXED), ("fp64", pc.FP64)):
+        b = pc.phicomb_batch_create(items, prec)
+        info = pc.phicomb_batch_info(b)
+        st, stats = pc.phicomb_batch_run(b, len(probs))      # first run captures the graph
+        if st != pc.OK:
+            raise RuntimeError(f"batch failed: {pc.phicomb_strerror(st)}")
+        ms = []
+        for _ in range(reps):
+            st, stats = pc.phicomb_batch_run(b, len(probs))
+            ms.append(stats[0].ms)
+        pc.phicomb_batch_destroy(b)
+        best = min(ms)
+        out[name] = {"solves_per_s": len(probs) / (best * 1e-3), "launch_ms": best,
+                     "predicted_ms": info["predicted_ms"], "groups": info["groups"],
+                     "workgroups": info["workgroups"],
+                     "max_s_int": max(s.s_int for s in stats),
+                     "fp32_terms": sum(s.fp32_terms for s in stats),
+                     "terms": sum(s.terms_S + s.terms_rec for s in stats)}
+    for o in ops:
+        o.close()
+    return out
+
+
 def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
     """Poisson request stream over a resident operator pool (70 % 2-D/3-D
     stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
@@ -265,6 +302,7 @@ def main(argv=None) -> int:
     op.close()
     if not args.no_extras:
         line["mixed_tol1e-6"] = bench_mixed(pc, wl, torch, reps=5)
+        line["batched"] = bench_batched(pc, wl, torch, reps=2)
         if args.serve_seconds > 0:
             line["served"] = bench_served(pc, wl, torch, args.serve_seconds, args.serve_rate,
                                           args.serve_slots)

@@ -227,6 +227,30 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double *part, do
     }
 }
 
+// Max of NV values over one workgroup, left in every thread (a grid of a
+// single workgroup needs no exchange through memory).
+template <int NV, int NT>
+__device__ __forceinline__ void workgroup_max(double (&v)[NV], double (*red)[2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = wave_max(v[j]);
+    __syncthreads();   // every wave has finished reading red from the last exchange
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            red[wave][j] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double r = red[0][j];
+        for (int w = 1; w < NT / 64; ++w)
+            r = nmax(r, red[w][j]);
+        v[j] = r;
+    }
+}
+
 // Max over all workgroups' partials, after grid_sync; every thread gets it.
 template <int NV, int NT>
 __device__ __forceinline__ void load_partials(const double *part, unsigned nblocks,

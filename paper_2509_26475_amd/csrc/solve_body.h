@@ -175,7 +175,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     };
 
     GridSync gs;
-    if (!grid_setup(gs, P.bar, &sh.ok, G)) {
+    // A single workgroup produces and consumes every row on one CU: its own
+    // stores, waited for, and a workgroup barrier are all it needs.
+    const bool single = (G == 1);
+    if (!single && !grid_setup(gs, P.bar, &sh.ok, G)) {
         finish(PHICOMB_EDEVICE, 0, 0, 0);
         return;
     }
@@ -183,6 +186,11 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     // publish this workgroup's maxima, cross the barrier, reduce all of them
     auto exchange = [&](auto &v) __attribute__((always_inline)) -> bool {
         constexpr int NV = std::extent<std::remove_reference_t<decltype(v)>>::value;
+        if (single) {
+            wait_own_stores();
+            workgroup_max<NV, kNT>(v, red);
+            return true;
+        }
         double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
         store_partials<NV, kNT>(v, pt, red, bid);
         if (!grid_sync(gs, &sh.ok))

@@ -161,6 +161,59 @@ def expm_multiply_aug(csr, t, beta, V) -> np.ndarray:
     return W
 
 
+_EXACT_Q = None
+
+
+def _exact_q_lib():
+    """Build (once, with gcc) and load the quadruple-precision augmented
+    exponential of exact_q.c."""
+    global _EXACT_Q
+    if _EXACT_Q is None:
+        import ctypes
+        import os
+        import subprocess
+        here = os.path.dirname(os.path.abspath(__file__))
+        out_dir = os.path.join(here, "_build")
+        os.makedirs(out_dir, exist_ok=True)
+        lib = os.path.join(out_dir, "libexact_q.so")
+        src = os.path.join(here, "exact_q.c")
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            subprocess.run(["gcc", "-O2", "-shared", "-fPIC", src, "-o", lib + ".tmp",
+                            "-lquadmath"], check=True)
+            os.replace(lib + ".tmp", lib)
+        L = ctypes.CDLL(lib)
+        P = ctypes.c_void_p
+        L.aug_expm_q.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_double, P, P, P]
+        L.aug_expm_q.restype = ctypes.c_int
+        _EXACT_Q = L
+    return _EXACT_Q
+
+
+def exact_dense_q(A, t, beta, V) -> np.ndarray:
+    """W[:, i] = sum_j beta_ij phi_j(t_i A) v_j from the augmented exponential
+    in __float128 (Taylor, scaling and squaring); dense A only."""
+    L = _exact_q_lib()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    n, P1 = V.shape
+    W = np.empty((n, len(t)))
+    for i, ti in enumerate(t):
+        b = np.ascontiguousarray(beta[i], dtype=np.float64)
+        w = np.empty(n)
+        rc = L.aug_expm_q(n, P1 - 1, A.ctypes.data, float(ti), b.ctypes.data, V.ctypes.data,
+                          w.ctypes.data)
+        assert rc == 0
+        W[:, i] = w
+    return W
+
+
+def rel1_cols(a, b) -> np.ndarray:
+    """Relative 1-norm error per column (the error measure of Table 1)."""
+    a = np.asarray(a).reshape(b.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    return np.abs(a - b).sum(axis=0) / np.abs(b).sum(axis=0)
+
+
 def rel2(a, b) -> float:
     """Relative 2-norm error ||a-b||/||b|| (Frobenius over all columns)."""
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))

@@ -222,3 +222,33 @@ def test_overflow_guard_and_invalid_inputs():
         op.solve(prm, pr.t, pr.beta, V, -1.0)
     assert e.value.status == pc.EINVAL
     op.close()
+
+
+# ------------------------------------------- second experiment (Sec. 5, Table 1)
+def test_second_experiment_chebyshev():
+    """Dense, highly non-normal collocation Laplacian (n = 99), p = 6, one
+    solve per t = 1e-4 .. 1e-1 at tol 2^-53: end to end (parameters from
+    the GPU) within 10x the paper's Table 1 errors against an exact
+    reference, and parity with the oracle at pinned parameters."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_phimv.json")))
+    for pr, env in zip(wl.exp2_problems()[:4], g["rel_err_1norm"][:4]):
+        say(f"[gpu] {pr.name}")
+        Wq = refs.exact_dense_q(pr.op.A, pr.t, pr.beta, pr.V)
+        Wg, sg, prm = gpu_solve(pr)
+        e_end = refs.rel1_cols(Wg, Wq)[0]
+        po = oracle.params(pr.op, pr.tol, pr.v)
+        Wo, so = oracle.solve(pr.op, pr.p, pr.r, pr.t, pr.beta, pr.V, pr.tol, po["shift"], po["s"])
+        Wp, sp_, _ = gpu_solve(pr, prm=po)
+        e_par = refs.rel2_cols(Wp, Wo)[0]
+        # where the method's own rounding error exceeds 1e-12 (tens of
+        # thousands of scaling steps on a non-normal matrix; Table 1 reports
+        # 1.2e-12 at t = 0.1), two correct FP64 evaluations differ by up to
+        # that error: the bar is the oracle's own error against the exact one
+        e_orc = refs.rel2_cols(Wo, Wq)[0]
+        say(f"      s_int={sg['s_int']} end-to-end rel1 err {e_end:.2e} (Table 1: {env:.1e}); "
+            f"pinned vs oracle {e_par:.2e} (oracle vs exact {e_orc:.2e})")
+        assert e_end <= 10 * env
+        assert sp_["s_int"] == so["s_int"]
+        assert e_par <= max(TOL_FP64, e_orc)

@@ -258,6 +258,40 @@ def config3(nside: int = 128, nonnormal: bool = False, tol: float = 1e-12) -> Pr
                    params_vector(op.n, 1), c)
 
 
+def chebyshev_laplacian(N: int = 100, L: float = 2.0) -> Dense:
+    """Chebyshev spectral collocation of d^2/dx^2 on [0, L] with homogeneous
+    Dirichlet conditions (Sec. 5, second experiment): the first-derivative
+    collocation matrix D on the N+1 Chebyshev points x_j = (cos(pi j/N)+1) L/2
+    (off-diagonal D_ij = (c_i/c_j) (-1)^(i+j) / (x_i - x_j), c_0 = c_N = 2,
+    c_j = 1 otherwise; diagonal = minus the off-diagonal row sum), squared,
+    interior rows and columns kept: A is (N-1) x (N-1), dense, non-normal,
+    eigenvalues on the negative real axis."""
+    j = np.arange(N + 1)
+    x = (np.cos(np.pi * j / N) + 1.0) * (L / 2.0)
+    c = np.where((j == 0) | (j == N), 2.0, 1.0) * (-1.0) ** j
+    dx = x[:, None] - x[None, :]
+    D = (c[:, None] / c[None, :]) / (dx + np.eye(N + 1))
+    D = D - np.diag(D.sum(axis=1))
+    A = (2.0 / L) ** 2 * (D @ D)
+    return Dense(np.ascontiguousarray(A[1:N, 1:N]))
+
+
+def exp2_problems(seed: int = 0, N: int = 100) -> List[Problem]:
+    """Second experiment of Sec. 5: the collocation Laplacian above (N = 100,
+    L = 2, n = 99), p = 6, one solve per t_i = 10^(i-5), i = 1..5 (Table 1
+    reports each t on its own), weights t_i^j (alpha = t_i), the same
+    v_j ~ N(0,1) for every t, tol = 2^-53."""
+    op = chebyshev_laplacian(N)
+    p = 6
+    V = _V_normal(op.n, p, seed)
+    out = []
+    for i in range(1, 6):
+        t = np.array([10.0 ** (i - 5)])
+        out.append(Problem(f"exp2_cheb_lap_99_t1e{i - 5}", op, p, 1, t, vandermonde(t, p), V,
+                           2.0 ** -53, params_vector(op.n, 1), t))
+    return out
+
+
 def config4(count: int = 256, seed: int = 0, side_range=(32, 256)) -> List[Problem]:
     """Batched uneven instances: 2-D kappa*Laplacians, side ~ U{32..256},
     kappa ~ logU[1e-2, 1e2], p ~ U{1,2,3}, r ~ U{1,2,3},
