@@ -122,9 +122,12 @@ def bench_batched(pc, wl, torch, reps: int) -> dict:
     out = {"workload": "256 kappa-Laplacians 2-D, side U{32..256}, p,r U{1,2,3}, tol 1e-8",
            "instances": len(probs)}
     for name, prec in (("mixed", pc.MIXED), ("fp64", pc.FP64)):
+        print(f"[bench] batched {name}: plan", file=sys.stderr, flush=True)
         b = pc.phicomb_batch_create(items, prec)
         info = pc.phicomb_batch_info(b)
         st, stats = pc.phicomb_batch_run(b, len(probs))      # first run captures the graph
+        print(f"[bench] batched {name}: first run {stats[0].ms:.0f} ms", file=sys.stderr,
+              flush=True)
         if st != pc.OK:
             raise RuntimeError(f"batch failed: {pc.phicomb_strerror(st)}")
         ms = []
@@ -141,6 +144,30 @@ def bench_batched(pc, wl, torch, reps: int) -> dict:
                      "terms": sum(s.terms_S + s.terms_rec for s in stats)}
     for o in ops:
         o.close()
+    return out
+
+
+def bench_exp2(pc, wl, torch) -> dict:
+    """Second experiment of the paper (collocation Laplacian, n = 99, dense,
+    p = 6, tol 2^-53), one solve per t = 1e-4 .. 1e-1 with parameters from
+    the GPU; accuracy against an exact reference is checked by the tests."""
+    out = {"workload": "chebyshev collocation Laplacian N=100 L=2 (n=99), p=6, tol 2^-53",
+           "t": [], "solve_ms": [], "s_int": []}
+    for pr in wl.exp2_problems()[:4]:
+        op = pc.Operator(pr.op)
+        prm = pc.phicomb_params(op.h, pr.tol, 61, pr.v, 1)
+        V = torch.from_numpy(pr.V).cuda()
+        W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
+        torch.cuda.synchronize()
+        print(f"[bench] second experiment t={pr.t[0]:g}: {st.ms:.0f} ms", file=sys.stderr,
+              flush=True)
+        out["t"].append(float(pr.t[0]))
+        out["solve_ms"].append(1e3 * (time.perf_counter() - t0))
+        out["s_int"].append(st.s_int)
+        op.close()
     return out
 
 
@@ -203,12 +230,28 @@ def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dic
             "mean_kernel_ms": float(np.mean(kernel_ms))}
 
 
+def dense_workload(wl):
+    """Dense non-normal operator of the served stream at its largest size:
+    upper triangular n = 2048, strictly upper N(0,1), diagonal -U(0, 50);
+    p = 3, r = 3, t_i = (i/3) * 10 / ||A||_inf, beta = 1, V ~ N(0,1),
+    tol 1e-10 (FP64)."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    op = wl.dense_upper_nonnormal(2048, rng)
+    t = (np.arange(1, 4) / 3.0) * 10.0 / _norm_inf(op)
+    V = np.ascontiguousarray(rng.standard_normal((4, op.n)).T)
+    return wl.Problem("dense_upper_2048", op, 3, 3, t, np.ones((3, 4)), V, 1e-10,
+                      wl.params_vector(op.n, 1))
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--kind", choices=["csr", "stencil"], default="csr")
+    ap.add_argument("--kind", choices=["csr", "stencil", "dense"], default="csr",
+                    help="operator of the headline workload; 'dense' runs the dense "
+                         "non-normal n = 2048 operator of the served stream instead")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision and served-stream measurements")
@@ -241,7 +284,10 @@ def main(argv=None) -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    pr = wl.config2(as_csr=(args.kind == "csr"))
+    if args.kind == "dense":
+        pr = dense_workload(wl)
+    else:
+        pr = wl.config2(as_csr=(args.kind == "csr"))
     op = pc.Operator(pr.op)
     V = torch.from_numpy(pr.V).cuda()
     W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
@@ -271,7 +317,8 @@ def main(argv=None) -> int:
     bytes_launch = float(np.mean([s["bytes_alg"] for s in stats]))
     achieved = bytes_launch / (ms_kernel * 1e-3) / 1e9
     kernel_name = f"solve_kernel<{args.kind},r={pr.r}>"
-    workload = f"convdiff2d_512_{args.kind}_p3_r3_tol1e-12"
+    workload = (f"convdiff2d_512_{args.kind}_p3_r3_tol1e-12" if args.kind != "dense"
+                else "dense_upper_nonnormal_2048_p3_r3_tol1e-10")
     traffic = measured_traffic(kernel_name, workload)
     line = {
         "metric": METRIC,
@@ -287,7 +334,9 @@ def main(argv=None) -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": workload, "n": pr.n, "p": pr.p, "r": pr.r,
-                   "operator": f"{args.kind} 5-point upwind convection-diffusion 512x512",
+                   "operator": (f"{args.kind} 5-point upwind convection-diffusion 512x512"
+                                if args.kind != "dense" else
+                                "dense upper-triangular non-normal 2048x2048 (MFMA)"),
                    "tol": pr.tol, "step": "Algorithm 1 + Algorithm 3"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -300,12 +349,27 @@ def main(argv=None) -> int:
         "shift": prm.shift, "s": prm.s,
     }
     op.close()
+
+    def progress(what, t_start):
+        print(f"[bench] {what} done in {time.perf_counter() - t_start:.1f} s", file=sys.stderr,
+              flush=True)
+
+    progress("headline workload", t0)
     if not args.no_extras:
+        t1 = time.perf_counter()
         line["mixed_tol1e-6"] = bench_mixed(pc, wl, torch, reps=5)
-        line["batched"] = bench_batched(pc, wl, torch, reps=2)
+        progress("mixed precision", t1)
+        t1 = time.perf_counter()
+        line["batched"] = bench_batched(pc, wl, torch, reps=1)
+        progress("batched", t1)
+        t1 = time.perf_counter()
+        line["exp2"] = bench_exp2(pc, wl, torch)
+        progress("second experiment", t1)
         if args.serve_seconds > 0:
+            t1 = time.perf_counter()
             line["served"] = bench_served(pc, wl, torch, args.serve_seconds, args.serve_rate,
                                           args.serve_slots)
+            progress("served stream", t1)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pr)
     else:

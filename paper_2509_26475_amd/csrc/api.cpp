@@ -39,6 +39,8 @@ void free_op(phicomb_op op) {
         return;
     if (op->mem)
         hipFree(op->mem);
+    if (op->dense_mem)
+        hipFree(op->dense_mem);
     if (op->ws.ptr)
         hipFree(op->ws.ptr);
     if (op->pinned)
@@ -251,11 +253,21 @@ int phicomb_op_create_dense(int64_t n, const double *A, phicomb_op *out) {
     phicomb_op op = new_op();
     if (!op)
         return PHICOMB_ENOMEM;
-    const int st = upload_csr(op, n, rp.data(), ci.data(), A);
+    // the CSR form serves Algorithm 1; the solve reads the row-major copy
+    int st = upload_csr(op, n, rp.data(), ci.data(), A);
+    if (st == PHICOMB_OK) {
+        const size_t bytes = sizeof(double) * (size_t)n * (size_t)n;
+        if (hipMalloc(&op->dense_mem, bytes) != hipSuccess)
+            st = PHICOMB_ENOMEM;
+        else if (hipMemcpy(op->dense_mem, A, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            st = PHICOMB_EDEVICE;
+    }
     if (st != PHICOMB_OK) {
         free_op(op);
         return st;
     }
+    op->dev.dense = (const double *)op->dense_mem;
+    op->dev.kind = kDense;
     *out = op;
     return PHICOMB_OK;
 }

@@ -57,6 +57,8 @@ __device__ __forceinline__ void run_layout(int layout, const SolveArgs &P, Solve
 
 // wg_group[b]: group of workgroup b; gfirst/gsize: first workgroup and size of
 // each group; glist[goff[g] .. goff[g+1]): the instances group g runs, in order.
+// ts[it][0..1]: device wall clock at the start and end of instance it (for
+// the cost model's calibration).
 template <int KIND, bool MIX>
 __global__ __launch_bounds__(kNT) void solve_batch_kernel(const SolveArgs *__restrict__ args,
                                                           const int *__restrict__ variant,
@@ -64,7 +66,8 @@ __global__ __launch_bounds__(kNT) void solve_batch_kernel(const SolveArgs *__res
                                                           const int *__restrict__ gfirst,
                                                           const int *__restrict__ gsize,
                                                           const int *__restrict__ goff,
-                                                          const int *__restrict__ glist) {
+                                                          const int *__restrict__ glist,
+                                                          long long *__restrict__ ts) {
     __shared__ SolveShared sh;
     const int g = wg_group[blockIdx.x];
     const unsigned G = (unsigned)gsize[g];
@@ -74,18 +77,22 @@ __global__ __launch_bounds__(kNT) void solve_batch_kernel(const SolveArgs *__res
         const SolveArgs &P = args[it];
         const int v = variant[it];
         const int layout = v % kLayouts;
+        if (bid == 0 && threadIdx.x == 0)
+            ts[2 * it] = wall_clock64();
         switch (v / kLayouts) {
         case 0: run_layout<KIND, 1, MIX>(layout, P, sh, G, bid); break;
         case 1: run_layout<KIND, 2, MIX>(layout, P, sh, G, bid); break;
         case 2: run_layout<KIND, 3, MIX>(layout, P, sh, G, bid); break;
         default: run_layout<KIND, 4, MIX>(layout, P, sh, G, bid); break;
         }
+        if (bid == 0 && threadIdx.x == 0)
+            ts[2 * it + 1] = wall_clock64();
         __syncthreads();   // the next instance reuses the shared state
     }
 }
 
 using BatchKernel = void (*)(const SolveArgs *, const int *, const int *, const int *,
-                             const int *, const int *, const int *);
+                             const int *, const int *, const int *, long long *);
 
 static BatchKernel pick_batch_kernel(int kind, bool mix) {
     if (kind == kStencil)
@@ -117,11 +124,22 @@ struct ItemCost {
     int gmax;       // most workgroups that still own 512 rows each
 };
 
-// One term on G workgroups, microseconds: barrier plus the term's bytes at
-// a per-CU streaming rate.
+// One term on G workgroups, microseconds: the exchange (a workgroup barrier
+// for G = 1, the grid barrier otherwise) plus the term's bytes at a per-CU
+// streaming rate.  The starting constants gave the best measured schedule
+// of the 256-instance benchmark batch on MI355X; the first run of a plan
+// refits them from the measured duration of every instance.
+struct Model {
+    double e1 = 1.5, bw1 = 25e3;              // G = 1: exchange (us), bytes per us
+    double e2 = 3.0, g2 = 0.006, bw2 = 25e3;  // G > 1
+};
+static thread_local Model t_model;
+
 static double term_us(const ItemCost &c, int G) {
-    const double barrier = (G == 1) ? 1.5 : 3.0 + 0.006 * G;
-    return barrier + c.bytes / ((double)G * 25e3);
+    const Model &m = t_model;
+    if (G == 1)
+        return m.e1 + c.bytes / m.bw1;
+    return m.e2 + m.g2 * G + c.bytes / ((double)G * m.bw2);
 }
 static double cost_us(const ItemCost &c, int G) { return c.terms * term_us(c, G); }
 
@@ -242,20 +260,29 @@ struct phicomb_batch_s {
     int device = 0;
     int count = 0;
     int kind = 0;
+    int precision = 0;
     bool mix = false;
+    bool tuned = false;
+    int cap = 0;                  // workgroups the launch may use
     std::vector<phicomb_op> ops;
     std::vector<int> p, r, s_int;
+    std::vector<ItemCost> cost;
+    Model model;
     Schedule sched;
     int wgs = 0;
-    void *mem = nullptr;          // device: args, tables, status words, work blocks
+    int ng = 0;
+    void *mem = nullptr;          // device: args, tables, status words, clocks, work blocks
     SolveArgs *args = nullptr;
     int *tables = nullptr;        // variant, wg_group, gfirst, gsize, goff, glist
-    int ng = 0;
     int *info_dev = nullptr;      // [count][8], gathered after the solve
-    int *info_host = nullptr;     // pinned copy
+    long long *ts_dev = nullptr;  // [count][2] wall clock at start / end of every instance
+    int *info_host = nullptr;     // pinned copies
+    long long *ts_host = nullptr;
+    double clock_khz = 0.0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool no_graph = false;
     BatchKernel kernel = nullptr;
 };
 
@@ -268,20 +295,146 @@ __global__ void batch_gather_info(const SolveArgs *__restrict__ args, int *__res
         out[i] = args[i / 8].info[i % 8];
 }
 
-void free_batch(phicomb_batch b) {
-    if (!b)
-        return;
+void drop_graph(phicomb_batch b) {
     if (b->exec)
         hipGraphExecDestroy(b->exec);
     if (b->graph)
         hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void free_batch(phicomb_batch b) {
+    if (!b)
+        return;
+    drop_graph(b);
     if (b->cap_stream)
         hipStreamDestroy(b->cap_stream);
     if (b->mem)
         hipFree(b->mem);
     if (b->info_host)
         hipHostFree(b->info_host);
+    if (b->ts_host)
+        hipHostFree(b->ts_host);
     delete b;
+}
+
+size_t table_ints(int count, int cap) { return (size_t)2 * count + cap + 3 * (size_t)cap + 1; }
+
+// Schedule with the plan's model, then the launch tables (the layout of an
+// instance depends on the size of its group).  Drops the captured graph.
+int build_plan(phicomb_batch b) {
+    t_model = b->model;
+    b->sched = make_schedule(b->cost, b->cap);
+    b->wgs = b->sched.wgs;
+    b->ng = (int)b->sched.gsize.size();
+    const int count = b->count, ng = b->ng;
+    std::vector<int> tab(table_ints(count, b->cap), 0);
+    int *t_variant = tab.data();
+    int *t_wg = t_variant + count;
+    int *t_gfirst = t_wg + b->wgs;
+    int *t_gsize = t_gfirst + ng;
+    int *t_goff = t_gsize + ng;
+    int *t_glist = t_goff + ng + 1;
+    int wg = 0, lo = 0;
+    for (int g = 0; g < ng; ++g) {
+        const int G = b->sched.gsize[g];
+        t_gfirst[g] = wg;
+        t_gsize[g] = G;
+        for (int k = 0; k < G; ++k)
+            t_wg[wg++] = g;
+        t_goff[g] = lo;
+        for (int it : b->sched.glist[g]) {
+            t_glist[lo++] = it;
+            const int64_t n = b->cost[it].n;
+            const int64_t rpt = (n + (int64_t)kNT * G - 1) / ((int64_t)kNT * G);
+            const int layout = rpt <= 1 ? 0 : rpt <= 2 ? 1 : rpt <= 4 ? 2 : kLayoutEmem;
+            t_variant[it] = (b->r[it] - 1) * kLayouts + layout;
+        }
+    }
+    t_goff[ng] = lo;
+    drop_graph(b);
+    if (hipMemcpy(b->tables, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return PHICOMB_EDEVICE;
+    return PHICOMB_OK;
+}
+
+// Least-squares fit of a + b x (returns false when degenerate or negative).
+bool fit_line(const std::vector<double> &x, const std::vector<double> &y, double &a, double &b) {
+    const size_t m = x.size();
+    if (m < 3)
+        return false;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (size_t i = 0; i < m; ++i) {
+        sx += x[i];
+        sy += y[i];
+        sxx += x[i] * x[i];
+        sxy += x[i] * y[i];
+    }
+    const double det = m * sxx - sx * sx;
+    if (!(det > 0.0))
+        return false;
+    b = (m * sxy - sx * sy) / det;
+    a = (sy - b * sx) / m;
+    return a > 0.0 && b > 0.0;
+}
+
+// After a run: the measured duration of every instance calibrates the model
+// (per-term time against the term's bytes, single workgroups and grids
+// separately) and the measured term counts replace the estimates; the plan is
+// rebuilt when its predicted makespan beats the measured one by 10 %.
+void tune(phicomb_batch b, double measured_ms) {
+    b->tuned = true;
+    std::vector<double> x1, y1, x2, y2;
+    std::vector<int> group_of(b->count, 0);
+    for (int g = 0; g < b->ng; ++g)
+        for (int it : b->sched.glist[g])
+            group_of[it] = g;
+    for (int it = 0; it < b->count; ++it) {
+        const int *info = b->info_host + 8 * it;
+        const double terms = (double)std::max(1, info[1] + info[2]);
+        b->cost[it].terms = terms;
+        const double us =
+            (double)(b->ts_host[2 * it + 1] - b->ts_host[2 * it]) / b->clock_khz * 1e3;
+        if (!(us > 0.0))
+            continue;
+        const int G = b->sched.gsize[group_of[it]];
+        if (G == 1) {
+            x1.push_back(b->cost[it].bytes);
+            y1.push_back(us / terms);
+        } else {
+            x2.push_back(b->cost[it].bytes / G);
+            y2.push_back(us / terms - b->model.g2 * G);
+        }
+    }
+    double a, c;
+    if (fit_line(x1, y1, a, c)) {
+        b->model.e1 = a;
+        b->model.bw1 = 1.0 / c;
+    }
+    if (fit_line(x2, y2, a, c)) {
+        b->model.e2 = a;
+        b->model.bw2 = 1.0 / c;
+    }
+    // adopt the refit only if it reproduces the run just measured
+    t_model = b->model;
+    double pred = 0.0;
+    for (int g = 0; g < b->ng; ++g) {
+        double t = 0.0;
+        for (int it : b->sched.glist[g])
+            t += cost_us(b->cost[it], b->sched.gsize[g]);
+        pred = std::max(pred, t);
+    }
+    pred *= 1e-3;
+    if (!(pred > 0.75 * measured_ms && pred < 1.25 * measured_ms)) {
+        b->model = Model();
+        t_model = b->model;
+        return;
+    }
+    const Schedule trial = make_schedule(b->cost, b->cap);
+    if (trial.makespan * 1e-3 < 0.9 * measured_ms)
+        build_plan(b);
 }
 
 }  // namespace
@@ -317,7 +470,8 @@ int phicomb_batch_create(int count, const phicomb_batch_item *items, int precisi
                 st = PHICOMB_EINVAL;
         if (st != PHICOMB_OK)
             break;
-        const int kind = q.op->dev.kind;
+        // dense operators run through their CSR form in a batch
+        const int kind = (q.op->dev.kind == kDense) ? kCsr : q.op->dev.kind;
         if (i == 0) {
             b->kind = kind;
             b->device = q.op->device;
@@ -331,11 +485,14 @@ int phicomb_batch_create(int count, const phicomb_batch_item *items, int precisi
         free_batch(b);
         return st;
     }
-    // workspace sizes and cost model
+    // workspace sizes and cost estimates
     std::vector<size_t> ws(count);
-    std::vector<ItemCost> cost(count);
-    const size_t sync_b = solve_sync_bytes();
+    b->cost.resize(count);
     size_t work_total = 0;
+    b->ops.resize(count);
+    b->p.resize(count);
+    b->r.resize(count);
+    b->s_int.resize(count);
     for (int i = 0; i < count; ++i) {
         const phicomb_batch_item &q = items[i];
         const int64_t n = q.op->dev.n;
@@ -351,27 +508,33 @@ int phicomb_batch_create(int count, const phicomb_batch_item *items, int precisi
         }
         const double steps = std::max(1.0, sc);
         const double k = taylor_terms(q.tol);
-        const double opb = (q.op->dev.kind == kCsr) ? 12.0 * q.op->nnz / (double)n : 0.0;
-        cost[i].terms = k * steps;
-        cost[i].bytes = (double)n * (24.0 * 2 * q.r + opb);
-        cost[i].n = n;
-        cost[i].gmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + kNT - 1) / kNT));
+        const double opb = (q.op->dev.kind != kStencil) ? 12.0 * q.op->nnz / (double)n : 0.0;
+        b->cost[i].terms = k * steps;
+        b->cost[i].bytes = (double)n * (24.0 * 2 * q.r + opb);
+        b->cost[i].n = n;
+        b->cost[i].gmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + kNT - 1) / kNT));
+        b->ops[i] = q.op;
+        b->p[i] = q.p;
+        b->r[i] = q.r;
     }
-    const int cap = device_cus(b->device) / kXcds * kXcds;
-    b->sched = make_schedule(cost, cap);
-    b->wgs = b->sched.wgs;
-    const int ng = (int)b->sched.gsize.size();
-    // device memory: args | variant | wg_group | gfirst | gsize | goff | glist | info | work
-    const size_t args_b = sizeof(SolveArgs) * count;
-    const size_t ntab = (size_t)count + b->wgs + 3 * (size_t)ng + 1 + count;
-    const size_t tab_b = (sizeof(int) * ntab + 255) & ~(size_t)255;
+    b->cap = device_cus(b->device) / kXcds * kXcds;
+    b->precision = precision;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;
+    b->clock_khz = (double)khz;
+    // device memory: args | tables | info | clocks | work
+    const size_t args_pad = (sizeof(SolveArgs) * count + 255) & ~(size_t)255;
+    const size_t tab_b = (sizeof(int) * table_ints(count, b->cap) + 255) & ~(size_t)255;
     const size_t info_b = (sizeof(int) * 8 * count + 255) & ~(size_t)255;
-    const size_t args_pad = (args_b + 255) & ~(size_t)255;
-    (void)sync_b;
-    const size_t total = args_pad + tab_b + info_b + work_total;
+    const size_t ts_b = (sizeof(long long) * 2 * count + 255) & ~(size_t)255;
+    const size_t total = args_pad + tab_b + info_b + ts_b + work_total;
     if (hipSetDevice(b->device) != hipSuccess || hipMalloc(&b->mem, total) != hipSuccess ||
         hipHostMalloc((void **)&b->info_host, sizeof(int) * 8 * count, hipHostMallocDefault) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc((void **)&b->ts_host, sizeof(long long) * 2 * count,
+                      hipHostMallocDefault) != hipSuccess) {
         free_batch(b);
         return PHICOMB_ENOMEM;
     }
@@ -379,17 +542,10 @@ int phicomb_batch_create(int count, const phicomb_batch_item *items, int precisi
     b->args = (SolveArgs *)base;
     b->tables = (int *)(base + args_pad);
     b->info_dev = (int *)(base + args_pad + tab_b);
-    char *work = base + args_pad + tab_b + info_b;
+    b->ts_dev = (long long *)(base + args_pad + tab_b + info_b);
+    char *work = base + args_pad + tab_b + info_b + ts_b;
     std::vector<SolveArgs> args(count);
-    std::vector<int> variant(count), group_of(count, 0);
-    for (int g = 0; g < ng; ++g)
-        for (int it : b->sched.glist[g])
-            group_of[it] = g;
     size_t off = 0;
-    b->ops.resize(count);
-    b->p.resize(count);
-    b->r.resize(count);
-    b->s_int.resize(count);
     for (int i = 0; i < count; ++i) {
         const phicomb_batch_item &q = items[i];
         st = build_solve_args(q.op, q.prm, q.p, q.r, q.t, q.beta, q.V, q.tol, precision, q.W,
@@ -399,48 +555,20 @@ int phicomb_batch_create(int count, const phicomb_batch_item *items, int precisi
             return st;
         }
         off += ws[i];
-        const int G = b->sched.gsize[group_of[i]];
-        const int64_t rows_per_thread = (q.op->dev.n + (int64_t)kNT * G - 1) / ((int64_t)kNT * G);
-        const int layout = rows_per_thread <= 1 ? 0
-                           : rows_per_thread <= 2 ? 1
-                           : rows_per_thread <= 4 ? 2
-                                                   : kLayoutEmem;
-        variant[i] = (q.r - 1) * kLayouts + layout;
-        b->ops[i] = q.op;
-        b->p[i] = q.p;
-        b->r[i] = q.r;
         b->s_int[i] = args[i].s_int;
     }
-    // tables
-    std::vector<int> tab(ntab);
-    int *t_variant = tab.data();
-    int *t_wg = t_variant + count;
-    int *t_gfirst = t_wg + b->wgs;
-    int *t_gsize = t_gfirst + ng;
-    int *t_goff = t_gsize + ng;
-    int *t_glist = t_goff + ng + 1;
-    std::copy(variant.begin(), variant.end(), t_variant);
-    int wg = 0, lo = 0;
-    for (int g = 0; g < ng; ++g) {
-        t_gfirst[g] = wg;
-        t_gsize[g] = b->sched.gsize[g];
-        for (int k = 0; k < b->sched.gsize[g]; ++k)
-            t_wg[wg++] = g;
-        t_goff[g] = lo;
-        for (int it : b->sched.glist[g])
-            t_glist[lo++] = it;
-    }
-    t_goff[ng] = lo;
-    if (hipMemcpy(b->args, args.data(), args_b, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->tables, tab.data(), sizeof(int) * ntab, hipMemcpyHostToDevice) !=
-            hipSuccess) {
+    if (hipMemcpy(b->args, args.data(), sizeof(SolveArgs) * count, hipMemcpyHostToDevice) !=
+        hipSuccess) {
         free_batch(b);
         return PHICOMB_EDEVICE;
     }
-    b->ng = ng;
-    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    st = build_plan(b);
+    if (st == PHICOMB_OK &&
+        hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        st = PHICOMB_EDEVICE;
+    if (st != PHICOMB_OK) {
         free_batch(b);
-        return PHICOMB_EDEVICE;
+        return st;
     }
     *out = b;
     return PHICOMB_OK;
@@ -456,13 +584,19 @@ static hipError_t enqueue_batch(phicomb_batch b, hipStream_t s) {
     const int *t_glist = t_goff + ng + 1;
     batch_sync_init<<<count, 256, 0, s>>>(b->args, count);
     const SolveArgs *a = b->args;
-    void *kargs[] = {(void *)&a,      (void *)&t_variant, (void *)&t_wg,   (void *)&t_gfirst,
-                     (void *)&t_gsize, (void *)&t_goff,    (void *)&t_glist};
+    long long *ts = b->ts_dev;
+    void *kargs[] = {(void *)&a,       (void *)&t_variant, (void *)&t_wg,
+                     (void *)&t_gfirst, (void *)&t_gsize,   (void *)&t_goff,
+                     (void *)&t_glist,  (void *)&ts};
     hipError_t e = hipLaunchKernel((const void *)b->kernel, dim3(b->wgs), dim3(kNT), kargs, 0, s);
     if (e != hipSuccess)
         return e;
     batch_gather_info<<<(count * 8 + 255) / 256, 256, 0, s>>>(b->args, b->info_dev, count);
-    return hipMemcpyAsync(b->info_host, b->info_dev, sizeof(int) * 8 * count,
+    e = hipMemcpyAsync(b->info_host, b->info_dev, sizeof(int) * 8 * count, hipMemcpyDeviceToHost,
+                       s);
+    if (e != hipSuccess)
+        return e;
+    return hipMemcpyAsync(b->ts_host, b->ts_dev, sizeof(long long) * 2 * count,
                           hipMemcpyDeviceToHost, s);
 }
 
@@ -473,8 +607,9 @@ int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats) {
     if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
         return PHICOMB_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    // the launch is captured once; a failed capture falls back to direct launches
-    if (!b->exec && !b->graph) {
+    // the launch is captured once per plan; a failed capture falls back to
+    // direct launches
+    if (!b->exec && !b->no_graph) {
         bool ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) ==
                   hipSuccess;
         if (ok) {
@@ -491,7 +626,7 @@ int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats) {
             }
         }
         if (!b->exec)
-            b->graph = (hipGraph_t)1;   // remember: no graph on this runtime
+            b->no_graph = true;
     }
     const int held = round_xcd(b->wgs);
     if (cu_acquire(b->device, held, held) != held)
@@ -535,6 +670,8 @@ int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats) {
             o.ms = ms;
         }
     }
+    if (!b->tuned && worst == PHICOMB_OK)
+        tune(b, ms);
     return worst;
 }
 
@@ -553,8 +690,6 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
 int phicomb_batch_destroy(phicomb_batch b) {
     if (!b)
         return PHICOMB_EINVAL;
-    if (b->graph == (hipGraph_t)1)
-        b->graph = nullptr;
     free_batch(b);
     return PHICOMB_OK;
 }

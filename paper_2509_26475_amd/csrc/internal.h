@@ -500,6 +500,7 @@ struct phicomb_op_s {
     int64_t nnz = 0;
     double norm_inf = 0.0;        // max_i sum_j |a_ij| (bounds FP32 intermediates)
     void *mem = nullptr;          // device storage of the operator
+    void *dense_mem = nullptr;    // dense operators: row-major n x n copy
     std::mutex mu;                // serialises solves on this operator
     phc::Workspace ws;            // grow-only workspace of blocking solves
     double *pinned = nullptr;     // small pinned host buffer for read-backs

@@ -205,13 +205,29 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         const double *x = col(k - 1);
         double *y = col(k);
         Ssq acc{0.0, 0.0};
-        for (int64_t row = lo + tid; row < hi; row += kPNT) {
-            const RowCtx rc = row_ctx<KIND>(A, row);
-            double w[1];
-            apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
-            const double val = (k == 1) ? w[0] / nv : w[0];   // A (v/||v||)
-            y[row] = val;
-            ssq_add(acc, val);
+        if constexpr (KIND == kDense) {
+            // dense rows: one wave per row, lanes across the row, wave sum
+            for (int64_t row = lo + (tid >> 6); row < hi; row += kPNT / 64) {
+                const double *arow = A.dense + row * n;
+                double sum = 0.0;
+                for (int64_t c = tid & 63; c < n; c += 64)
+                    sum += arow[c] * x[c];
+                sum = wave_sum(sum);
+                if ((tid & 63) == 0) {
+                    const double val = (k == 1) ? sum / nv : sum;   // A (v/||v||)
+                    y[row] = val;
+                    ssq_add(acc, val);
+                }
+            }
+        } else {
+            for (int64_t row = lo + tid; row < hi; row += kPNT) {
+                const RowCtx rc = row_ctx<KIND>(A, row);
+                double w[1];
+                apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
+                const double val = (k == 1) ? w[0] / nv : w[0];   // A (v/||v||)
+                y[row] = val;
+                ssq_add(acc, val);
+            }
         }
         const double Lk = ssq_log(exchange(acc));
         if (!alive) {
@@ -271,16 +287,29 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         }
         const double *x = col(k - 1);
         double *y = col(k);
-        for (int64_t row = lo + tid; row < hi; row += kPNT) {
-            const RowCtx rc = row_ctx<KIND>(A, row);
-            double w[1];
-            apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
-            y[row] = w[0] / s0;
+        if constexpr (KIND == kDense) {
+            for (int64_t row = lo + (tid >> 6); row < hi; row += kPNT / 64) {
+                const double *arow = A.dense + row * n;
+                double sum = 0.0;
+                for (int64_t c = tid & 63; c < n; c += 64)
+                    sum += arow[c] * x[c];
+                sum = wave_sum(sum);
+                if ((tid & 63) == 0)
+                    y[row] = sum / s0;
+            }
+        } else {
+            for (int64_t row = lo + tid; row < hi; row += kPNT) {
+                const RowCtx rc = row_ctx<KIND>(A, row);
+                double w[1];
+                apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
+                y[row] = w[0] / s0;
+            }
         }
     }
 
     // ---- objective f(z) = ||sum_k b_k z^(m-k) V_k||^(1/m); every row of the
-    //      basis read here was written by this same thread
+    //      basis read here was written inside this workgroup, before the
+    //      workgroup barrier that opens each evaluation
     auto objective = [&](double z) __attribute__((always_inline)) -> double {
         __syncthreads();
         if (tid <= m) {
@@ -384,12 +413,13 @@ double binom_double(int m, int k) {
 
 int max_params_grid(int kind, int device) {
     static std::mutex mu;
-    static int cached[2][64] = {};
+    static int cached[3][64] = {};
     std::lock_guard<std::mutex> g(mu);
-    int &c = cached[kind == kStencil ? 0 : 1][device & 63];
+    int &c = cached[kind == kStencil ? 0 : kind == kDense ? 2 : 1][device & 63];
     if (c > 0)
         return c;
     const void *fn = (kind == kStencil) ? (const void *)params_kernel<kStencil>
+                     : (kind == kDense) ? (const void *)params_kernel<kDense>
                                         : (const void *)params_kernel<kCsr>;
     int per_cu = 0;
     hipDeviceProp_t prop;
@@ -458,9 +488,12 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     const int maxg = max_params_grid(op->dev.kind, op->device);
     if (maxg < 1)
         return PHICOMB_EDEVICE;
-    const int64_t G = std::min<int64_t>(maxg, (n + kPNT - 1) / kPNT);
+    // dense rows are spread so that every wave has at most two of them
+    const int64_t rows_per_wg = (op->dev.kind == kDense) ? 16 : kPNT;
+    const int64_t G = std::min<int64_t>(maxg, (n + rows_per_wg - 1) / rows_per_wg);
     const int held = round_xcd(G);   // at most ceil(G/8) of the grid lands on any XCD
     const void *fn = (op->dev.kind == kStencil) ? (const void *)params_kernel<kStencil>
+                     : (op->dev.kind == kDense) ? (const void *)params_kernel<kDense>
                                                 : (const void *)params_kernel<kCsr>;
     if (cu_acquire(op->device, held, held) != held)
         return PHICOMB_EDEVICE;

@@ -108,7 +108,9 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
                                 int terms_S, int terms_rec, int s_int, int f32_rec) {
     const double w = 8.0, N = (double)n;
     const double cS = (double)(p + 1) * r, cR = 2.0 * r;
-    const double opb = (op.kind == kCsr) ? (12.0 * (double)nnz + 4.0 * (N + 1)) : 0.0;
+    const double opb = (op.kind == kCsr)     ? (12.0 * (double)nnz + 4.0 * (N + 1))
+                       : (op.kind == kDense) ? 8.0 * N * N
+                                             : 0.0;
     double b = w * N * (p + 1) + 2 * w * N * cS;                        // V -> S, D
     b += (terms_S - 1) * (4 * w * N * cS + w * N * (p + 1) + opb);     // S-series terms
     b += 3 * w * N * r + opb;                                           // recover exp(tA/s) v0
@@ -127,8 +129,36 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
 // private frame with no scratch traffic in their code (up to kFrameOk
 // bytes); spilling ones have hundreds.
 constexpr size_t kFrameOk = 64;
+template <int R>
+static KernelFn dense_kernel() { return solve_kernel<kDense, R, 1, true, false>; }
+
+// Dense operators: at most kDenseRows rows per workgroup (one workgroup up to
+// n = kDenseRows), else 32 rows per workgroup so that the k range of every
+// row tile is split over the waves; FP64 only.
+static int64_t dense_grid(int64_t n) { return n <= kDenseRows ? 1 : (n + 31) / 32; }
+
 static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_needed1, int cap,
                                int64_t *G) {
+    if (op->dev.kind == kDense) {
+        KernelFn f = nullptr;
+        switch (r) {
+        case 1: f = dense_kernel<1>(); break;
+        case 2: f = dense_kernel<2>(); break;
+        case 3: f = dense_kernel<3>(); break;
+        case 4: f = dense_kernel<4>(); break;
+        default: return nullptr;
+        }
+        const int maxg = std::min(max_coresident(f, op->device), cap);
+        if (maxg < 1)
+            return nullptr;
+        // the grid keeps at most kDenseRows rows per workgroup
+        const int64_t need = dense_grid(op->dev.n);
+        const int64_t gmin = (op->dev.n + kDenseRows - 1) / kDenseRows;
+        if (gmin > maxg)
+            return nullptr;
+        *G = std::min<int64_t>(need, maxg);
+        return f;
+    }
     const int kind = (op->dev.kind == kCsr && op->dev.max_row_nnz <= kCacheNnz) ? kCsrCached
                                                                                   : op->dev.kind;
     for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
@@ -253,8 +283,11 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
     const int cus = device_cus(op->device);
     // Persistent launches on one device draw workgroup slots from a shared
     // ledger so that concurrent solves never exceed co-residency together.
-    const int want = (int)std::min<int64_t>(cus, wgs_needed1);
-    const int floor_g = (cu_floor > 0) ? std::min(want, cu_floor) : want;
+    const bool dense = (op->dev.kind == kDense);
+    const int want = (int)std::min<int64_t>(cus, dense ? dense_grid(n) : wgs_needed1);
+    int floor_g = (cu_floor > 0) ? std::min(want, cu_floor) : want;
+    if (dense)   // at most kDenseRows rows per workgroup
+        floor_g = std::max<int>(floor_g, (int)std::min<int64_t>(want, (n + kDenseRows - 1) / kDenseRows));
     const int granted = cu_acquire(op->device, want, floor_g);
     if (granted < 1)
         return PHICOMB_EDEVICE;

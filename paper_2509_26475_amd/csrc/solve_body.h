@@ -104,6 +104,72 @@ __device__ __forceinline__ void for_rows(int64_t lo, int64_t hi, F &&f) {
 // partial sums, the stopping test and everything carried across steps.
 constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predecessor
 
+// ------------------------------------------------------------ dense operator
+// A dense operator (row-major n x n) is applied per Taylor term to every
+// column the term needs at once: the workgroup computes the products of its
+// (at most kDenseRows) rows with FP64 MFMA 16x16x4 tiles, the k range split
+// over the waves when there are fewer tiles than waves, the partial tiles
+// summed in LDS; the row owners then read their products from LDS.
+// v_mfma_f64_16x16x4f64 lane layout (checked on the device): A operand
+// A[l % 16][l / 16], B operand B[l / 16][l % 16], result element v of lane l
+// is D[l / 16 + 4 v][l % 16].
+constexpr int kDenseRows = 128;   // rows per workgroup at most
+constexpr int kDenseCols = 32;    // columns per product at most ((p+1) r)
+constexpr int kSolveWaves = kNT / 64;
+
+struct DenseShared {
+    double Y[kDenseRows][kDenseCols + 1];   // products of the workgroup's rows
+    double part[2 * kSolveWaves][16][17];        // partial 16 x 16 tiles
+};
+
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+// Y[i][c] = sum_k A[lo+i][k] X[c n + k] - shift X[c n + lo + i],
+// i < hi - lo, c < ncols.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void dense_products(const double *__restrict__ Ad, int64_t n,
+                                               int64_t lo, int64_t hi,
+                                               const double *__restrict__ X, int ncols,
+                                               double shift, DenseShared &ds) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rows = (int)(hi - lo);
+    const int RT = (rows + 15) / 16, CT = (ncols + 15) / 16;
+    const int tiles = RT * CT;
+    const int KS = tiles >= kSolveWaves ? 1 : kSolveWaves / tiles;   // k slices per tile
+    const int64_t kchunk = ((n + KS - 1) / KS + 3) / 4 * 4;
+    for (int task = wave; task < tiles * KS; task += kSolveWaves) {
+        const int tile = task % tiles, ks = task / tiles;
+        const int rt = tile % RT, ct = tile / RT;
+        const int64_t row = lo + rt * 16 + (lane & 15);
+        const int col = ct * 16 + (lane & 15);
+        const bool rok = row < hi, cok = col < ncols;
+        const double *arow = Ad + (rok ? row : lo) * n;
+        const double *xcol = X + (int64_t)(cok ? col : 0) * n;
+        const int64_t kb = ks * kchunk, ke = std::min<int64_t>(n, kb + kchunk);
+        mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        // unrolled so that the loads of several steps are in flight together
+#pragma unroll 8
+        for (int64_t k = kb + (lane >> 4); k - (lane >> 4) < ke; k += 4) {
+            const bool kok = k < ke;
+            const double a = (rok && kok) ? arow[k] : 0.0;
+            const double b = (cok && kok) ? xcol[k] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            ds.part[task][(lane >> 4) + 4 * v][lane & 15] = acc[v];
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * ncols; e += kNT) {
+        const int i = e / ncols, c = e % ncols;
+        const int tile = (i >> 4) + RT * (c >> 4);
+        double sum = 0.0;
+        for (int ks = 0; ks < KS; ++ks)
+            sum += ds.part[tile + ks * tiles][i & 15][c & 15];
+        ds.Y[i][c] = sum - shift * X[(int64_t)c * n + lo + i];
+    }
+    __syncthreads();
+}
+
 // Workgroup-shared state of one solve.
 struct SolveShared {
     double Mk[kRMax][kPMax1][kPMax1];   // J_step^(k-1) / k!
@@ -159,13 +225,29 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             load_cached_row(A, row, crow[decltype(q)::value]);
         });
+    DenseShared *dsp = nullptr;
+    if constexpr (KIND == kDense) {
+        __shared__ DenseShared dense_lds;
+        dsp = &dense_lds;
+    }
+    // dense operator: products of this workgroup's rows for the coming term
+    auto dense_pass = [&](const double *X, int ncols, double shift)
+                          __attribute__((always_inline)) {
+        if constexpr (KIND == kDense)
+            dense_products(A.dense, n, lo, hi, X, ncols, shift, *dsp);
+    };
     auto opr = [&](int64_t row, auto q, const auto *X, int col0, double shift,
                    auto &y) __attribute__((always_inline)) {
         using Y = std::remove_reference_t<decltype(y)>;
         constexpr int NC = std::extent<Y>::value;
         using TA = std::remove_extent_t<Y>;
         using TX = std::remove_cv_t<std::remove_pointer_t<decltype(X)>>;
-        if constexpr (CACHED) {
+        if constexpr (KIND == kDense) {
+            // products computed by dense_products for this term
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] = (TA)dsp->Y[row - lo][col0 + j];
+        } else if constexpr (CACHED) {
             apply_cached<NC, TX, TA>(crow[decltype(q)::value], (unsigned)row, X, n, col0, shift,
                                      y);
         } else {
@@ -264,6 +346,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         const double *Uo = par ? P.U1 : P.U0;
         double *Un = par ? P.U0 : P.U1;
         double mx[2] = {0.0, 0.0};
+        dense_pass(Uo, P.cS, P.xi);
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             double vr[kPMax1];   // reordered v: vr[b] = v_perm(b)(row)
 #pragma unroll
@@ -319,6 +402,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     double nF = 0.0;
     {
         double mx[1] = {0.0};
+        dense_pass(P.S, R, 0.0);
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             double y[R];
             opr(row, q, P.S, 0, 0.0, y);
@@ -387,6 +471,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             const float *Fo32 = par ? P.Uf1 : P.Uf0;
             float *Fn32 = par ? P.Uf0 : P.Uf1;
             double mx[2] = {0.0, 0.0};
+            dense_pass(Fo, 2 * R, P.xi);
             for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
                 double f[2 * R];
                 if (MIX && in32) {
