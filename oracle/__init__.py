@@ -50,9 +50,9 @@ def build(force: bool = True) -> str:
 
 
 class _Op(C.Structure):
-    _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("rank", C.c_int32),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
-                ("dense", C.c_void_p)]
+                ("dense", C.c_void_p), ("lr_u", C.c_void_p), ("lr_w", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -133,6 +133,14 @@ class Operator:
             A = np.ascontiguousarray(op.A, dtype=np.float64)
             self.keep.append(A)
             s.n, s.kind, s.dense = A.shape[0], 1, A.ctypes.data
+        elif kind == "lowrank":
+            U = np.ascontiguousarray(op.U, dtype=np.float64)
+            W = np.ascontiguousarray(op.W, dtype=np.float64)
+            if U.shape != W.shape or U.shape[1] > 16:
+                raise ValueError("low-rank operator: U and W must be n x r, r <= 16")
+            self.keep += [U, W]
+            s.n, s.kind, s.rank = U.shape[0], 2, U.shape[1]
+            s.lr_u, s.lr_w = U.ctypes.data, W.ctypes.data
         else:
             rp, ci, va = op.csr()
             rp = np.ascontiguousarray(rp, dtype=np.int32)

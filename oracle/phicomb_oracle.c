@@ -50,12 +50,14 @@
 
 typedef struct {
     int64_t n;
-    int32_t kind;             /* 0: CSR, 1: dense row-major */
-    int32_t pad;
+    int32_t kind;             /* 0: CSR, 1: dense row-major, 2: low rank U W^T */
+    int32_t rank;             /* low rank: columns of U and W */
     const int32_t *rowptr;    /* CSR: n+1 */
     const int32_t *col;       /* CSR: nnz */
     const double *val;        /* CSR: nnz */
     const double *dense;      /* dense: n*n row-major */
+    const double *lr_u;       /* low rank: U, n x rank row-major */
+    const double *lr_w;       /* low rank: W, n x rank row-major */
 } orc_op;
 
 typedef struct {
@@ -81,10 +83,30 @@ typedef struct {
 
 /* ---------------------------------------------------------------- basics */
 
-/* y = A x (row sums in stored order). */
+/* y = A x (row sums in stored order).  The low-rank operator of the third
+ * experiment (Sec. 5) is applied matrix-free as x -> U (W^T x): first the
+ * rank inner products c_k = sum_i W_ik x_i (ascending i), then y_i =
+ * sum_k U_ik c_k. */
 static void apply_A(const orc_op *A, const double *x, double *y)
 {
     const int64_t n = A->n;
+    if (A->kind == 2) {
+        const int r = A->rank;
+        double c[16];
+        for (int k = 0; k < r; ++k) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                acc += A->lr_w[i * r + k] * x[i];
+            c[k] = acc;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k)
+                acc += A->lr_u[i * r + k] * c[k];
+            y[i] = acc;
+        }
+        return;
+    }
     if (A->kind == 0) {
         for (int64_t i = 0; i < n; ++i) {
             double acc = 0.0;

@@ -207,6 +207,48 @@ def exact_dense_q(A, t, beta, V) -> np.ndarray:
     return W
 
 
+def phi_matrix_mp(k: int, X: np.ndarray, dps: int = 60):
+    """phi_k(X) for a small square X: the (1, k+1) block of the exponential of
+    the block matrix with X in the corner and identities on the block
+    superdiagonal (the standard augmented form), at dps digits."""
+    r = X.shape[0]
+    N = r * (k + 1)
+    with mpmath.workdps(dps):
+        B = mpmath.zeros(N, N)
+        for a in range(r):
+            for b in range(r):
+                B[a, b] = mpmath.mpf(X[a, b])
+        for blk in range(k):
+            for a in range(r):
+                B[blk * r + a, (blk + 1) * r + a] = 1
+        E = mpmath.expm(B)
+        return [[E[a, k * r + b] for b in range(r)] for a in range(r)]
+
+
+def lowrank_exact(op, t: float, beta_i, V, dps: int = 60) -> np.ndarray:
+    """w = sum_j beta_j phi_j(tA) v_j for A = U W^T in closed form (Sec. 5,
+    third experiment): sum_j beta_j v_j / j! + U (t sum_j beta_j phi_{j+1}(tM)
+    (W^T v_j)); the small phi_{j+1}(tM) at dps digits."""
+    U, W, M = op.U, op.W, op.M
+    P1 = V.shape[1]
+    r = M.shape[0]
+    with mpmath.workdps(dps):
+        acc = [mpmath.mpf(0)] * r
+        for j in range(P1):
+            phi = phi_matrix_mp(j + 1, np.asarray(M) * t, dps)
+            wv = W.T @ V[:, j]          # r inner products in double (inputs are double)
+            for a in range(r):
+                s = mpmath.mpf(0)
+                for b in range(r):
+                    s += phi[a][b] * mpmath.mpf(wv[b])
+                acc[a] += mpmath.mpf(beta_i[j]) * mpmath.mpf(t) * s
+        coef = np.array([float(x) for x in acc])
+    w = U @ coef
+    for j in range(P1):
+        w = w + beta_i[j] * V[:, j] / math.factorial(j)
+    return w
+
+
 def rel1_cols(a, b) -> np.ndarray:
     """Relative 1-norm error per column (the error measure of Table 1)."""
     a = np.asarray(a).reshape(b.shape[0], -1)

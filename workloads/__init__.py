@@ -33,7 +33,8 @@ __all__ = [
     "Stencil", "Dense", "Problem", "stencil_to_csr", "laplacian_2d",
     "laplacian_3d", "convdiff_2d_upwind", "dense_upper_nonnormal",
     "config1", "config2", "config3", "config4", "config5_stream",
-    "small_problem", "params_vector",
+    "small_problem", "params_vector", "LowRank", "dct2_basis", "lowrank_cores",
+    "lowrank_operator", "exp3_problem", "EXP3_SHAPES",
 ]
 
 
@@ -290,6 +291,62 @@ def exp2_problems(seed: int = 0, N: int = 100) -> List[Problem]:
         out.append(Problem(f"exp2_cheb_lap_99_t1e{i - 5}", op, p, 1, t, vandermonde(t, p), V,
                            2.0 ** -53, params_vector(op.n, 1), t))
     return out
+
+
+@dataclasses.dataclass
+class LowRank:
+    """Matrix-free A = U W^T (third experiment of Sec. 5): U, W are n x r."""
+    U: np.ndarray
+    W: np.ndarray
+    M: np.ndarray        # the r x r core, W = U M^T
+    kind: str = "lowrank"
+
+    @property
+    def n(self) -> int:
+        return self.U.shape[0]
+
+
+def dct2_basis(n: int, r: int) -> np.ndarray:
+    """First r columns of the orthonormal DCT-II matrix:
+    U_ik = sqrt(2/n) a_k cos(pi (i + 1/2) k / n), a_0 = 1/sqrt(2), a_k = 1."""
+    i = np.arange(n)[:, None] + 0.5
+    k = np.arange(r)[None, :]
+    a = np.where(k == 0, 1.0 / math.sqrt(2.0), 1.0)
+    return np.ascontiguousarray(math.sqrt(2.0 / n) * a * np.cos(np.pi * i * k / n))
+
+
+def lowrank_cores() -> dict:
+    """The three cores of the third experiment (Sec. 5): M1 skew-symmetric
+    (normal A, eigenvalues +-10i), M2 upper triangular with a 1e5 coupling
+    (non-normal), M3 Moler's 3 x 3 core (eigenvalues about -63.4, -6.2,
+    -0.11, departure from normality ~2.8e10)."""
+    a, b, c, d, e = 2e10, 4e8 / 6.0, 200.0 / 3.0, 3.0, 1e-8
+    return {
+        "M1": np.array([[0.0, 10.0], [-10.0, 0.0]]),
+        "M2": np.array([[-1.0, 1e5], [0.0, -10.0]]),
+        "M3": np.array([[0.0, e, 0.0], [-(a + b), -d, a], [c, 0.0, -c]]),
+    }
+
+
+def lowrank_operator(core: np.ndarray, n: int) -> LowRank:
+    U = dct2_basis(n, core.shape[0])
+    return LowRank(U, np.ascontiguousarray(U @ core.T), np.asarray(core, dtype=np.float64))
+
+
+# sizes and p of the three cores in the paper (n, p)
+EXP3_SHAPES = {"M1": (200000, 3), "M2": (400000, 4), "M3": (500000, 2)}
+
+
+def exp3_problem(core_name: str, t: float, n: Optional[int] = None, seed: int = 0) -> Problem:
+    """One solve of the third experiment: A = U W^T with the named core, the
+    paper's n and p (or a given n), alpha = 1 (beta_j = 1), V ~ N(0,1),
+    tol = 2^-53, a single abscissa t."""
+    n0, p = EXP3_SHAPES[core_name]
+    n = n0 if n is None else n
+    op = lowrank_operator(lowrank_cores()[core_name], n)
+    ta = np.array([float(t)])
+    return Problem(f"exp3_{core_name}_n{n}_t{t:g}", op, p, 1, ta, np.ones((1, p + 1)),
+                   _V_normal(n, p, seed), 2.0 ** -53, params_vector(n, 1), np.ones(1))
 
 
 def config4(count: int = 256, seed: int = 0, side_range=(32, 256)) -> List[Problem]:
