@@ -99,6 +99,9 @@ def bench_mixed(pc, wl, torch, reps: int) -> list:
             st = sts[-1]
             row[name + "_solves_per_s"] = 1.0 / dt
             row[name + "_kernel_ms"] = st.ms
+            # algorithmic bytes over the kernel time, against the HBM peak
+            row[name + "_achieved_GBps"] = st.bytes_alg / (st.ms * 1e-3) / 1e9
+            row[name + "_hbm_frac"] = row[name + "_achieved_GBps"] / HBM_PEAK_GBS
             if prec == pc.MIXED:
                 row["fp32_term_fraction"] = st.fp32_terms / max(1, st.terms_S + st.terms_rec)
         row["mixed_over_fp64"] = row["mixed_solves_per_s"] / row["fp64_solves_per_s"]
