@@ -174,6 +174,46 @@ def bench_exp2(pc, wl, torch) -> dict:
     return out
 
 
+def bench_exp3(pc, wl, torch) -> dict:
+    """Third experiment of the paper (A = U W^T, DCT-II basis, cores M1-M3 at
+    the paper's n and p, alpha = 1, tol 2^-53): parameters (Algorithm 1) and
+    solve (Algorithm 3) per (core, t) on the GPU, timed end to end like the
+    paper's Tables 2-4; accuracy against the closed form is checked by the
+    tests."""
+    cases = [("M1", 0.1), ("M1", 1.0), ("M1", 10.0), ("M1", 50.0), ("M1", 100.0),
+             ("M2", 0.1), ("M2", 1.0), ("M2", 10.0), ("M2", 50.0), ("M2", 100.0),
+             ("M3", 1e-5), ("M3", 1e-3)]
+    out = {"workload": "low-rank A = U W^T (DCT-II U, W = U M^T); M1 n=2e5 p=3, "
+                       "M2 n=4e5 p=4, M3 n=5e5 p=2; alpha=1, tol 2^-53",
+           "core": [], "t": [], "params_ms": [], "solve_ms": [], "total_ms": [], "s_int": []}
+    ops = {}
+    for core, t in cases:
+        pr = wl.exp3_problem(core, t, seed=0)
+        if core not in ops:
+            ops[core] = pc.Operator(pr.op)
+        op = ops[core]
+        V = torch.from_numpy(pr.V).cuda()
+        W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prm = pc.phicomb_params(op.h, pr.tol, 61, pr.v, 1)
+        t1 = time.perf_counter()
+        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(f"[bench] third experiment {core} t={t:g}: s_int={st.s_int} "
+              f"{1e3 * (t2 - t0):.1f} ms", file=sys.stderr, flush=True)
+        out["core"].append(core)
+        out["t"].append(t)
+        out["params_ms"].append(1e3 * (t1 - t0))
+        out["solve_ms"].append(1e3 * (t2 - t1))
+        out["total_ms"].append(1e3 * (t2 - t0))
+        out["s_int"].append(st.s_int)
+    for op in ops.values():
+        op.close()
+    return out
+
+
 def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
     """Poisson request stream over a resident operator pool (70 % 2-D/3-D
     stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
@@ -368,6 +408,9 @@ def main(argv=None) -> int:
         t1 = time.perf_counter()
         line["exp2"] = bench_exp2(pc, wl, torch)
         progress("second experiment", t1)
+        t1 = time.perf_counter()
+        line["exp3"] = bench_exp3(pc, wl, torch)
+        progress("third experiment", t1)
         if args.serve_seconds > 0:
             t1 = time.perf_counter()
             line["served"] = bench_served(pc, wl, torch, args.serve_seconds, args.serve_rate,

@@ -120,6 +120,16 @@ int phicomb_op_create_stencil(int dim, const int32_t grid[3], const double coef[
 /* Dense n x n matrix, host row-major.  Products use FP64 MFMA. */
 int phicomb_op_create_dense(int64_t n, const double *A, phicomb_op *out);
 
+/* Low-rank operator A = U W^T (Sec. 5, third experiment: a fixed orthonormal
+ * basis U and W = U M^T for a small core M), applied matrix-free as
+ * x -> U (W^T x) with O(n rank) work per product.  U and W: host arrays,
+ * row-major n x rank, copied to the device.  1 <= rank <= 16, n < 2^31;
+ * a solve additionally needs rank * max((p+1) r + r, 2r) <= 256 (EINVAL
+ * otherwise).  The batched entry points do not take this kind (EINVAL).
+ * EINVAL on a bad size or a non-finite entry. */
+int phicomb_op_create_lowrank(int64_t n, int rank, const double *U, const double *W,
+                              phicomb_op *out);
+
 int phicomb_op_destroy(phicomb_op op);
 int64_t phicomb_op_n(phicomb_op op);
 

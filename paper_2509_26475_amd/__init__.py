@@ -75,6 +75,7 @@ def _lib():
             "phicomb_op_create_csr": ([I64, P, P, P, P], I32),
             "phicomb_op_create_stencil": ([I32, P, P, D, P], I32),
             "phicomb_op_create_dense": ([I64, P, P], I32),
+            "phicomb_op_create_lowrank": ([I64, I32, P, P, P], I32),
             "phicomb_op_destroy": ([P], I32),
             "phicomb_op_n": ([P], I64),
             "phicomb_params": ([P, D, I32, P, C.c_uint64, P, P], I32),
@@ -147,6 +148,19 @@ def phicomb_op_create_dense(n: int, A) -> C.c_void_p:
     a = np.ascontiguousarray(A, dtype=np.float64)
     h = C.c_void_p()
     _check(_lib().phicomb_op_create_dense(n, _np_ptr(a), C.byref(h)), "phicomb_op_create_dense")
+    return h
+
+
+def phicomb_op_create_lowrank(n: int, U, W) -> C.c_void_p:
+    """A = U W^T applied matrix-free; U, W host arrays n x rank (rank <= 16)."""
+    _require_gpu()
+    u = np.ascontiguousarray(U, dtype=np.float64)
+    w = np.ascontiguousarray(W, dtype=np.float64)
+    if u.ndim != 2 or u.shape != w.shape or u.shape[0] != n:
+        raise ValueError("U and W must both be n x rank")
+    h = C.c_void_p()
+    _check(_lib().phicomb_op_create_lowrank(n, u.shape[1], _np_ptr(u), _np_ptr(w), C.byref(h)),
+           "phicomb_op_create_lowrank")
     return h
 
 
@@ -264,7 +278,7 @@ def _check_device_tensor(x, shape, name):
 # ---------------------------------------------------------------- conveniences
 class Operator:
     """Resident operator handle built from a workloads description
-    (Stencil, CSR or Dense)."""
+    (Stencil, CSR, Dense or LowRank)."""
 
     def __init__(self, desc):
         kind = desc.kind
@@ -272,6 +286,8 @@ class Operator:
             self.h = phicomb_op_create_stencil(desc.dim, desc.grid, desc.coef, desc.superdiag)
         elif kind == "dense":
             self.h = phicomb_op_create_dense(desc.n, desc.A)
+        elif kind == "lowrank":
+            self.h = phicomb_op_create_lowrank(desc.n, desc.U, desc.W)
         else:
             rp, ci, va = desc.csr()
             self.h = phicomb_op_create_csr(len(rp) - 1, rp, ci, va)

@@ -272,6 +272,55 @@ int phicomb_op_create_dense(int64_t n, const double *A, phicomb_op *out) {
     return PHICOMB_OK;
 }
 
+int phicomb_op_create_lowrank(int64_t n, int rank, const double *U, const double *W,
+                              phicomb_op *out) {
+    if (!out || n < 1 || n >= INT32_MAX || rank < 1 || rank > kLrRankMax || !U || !W)
+        return PHICOMB_EINVAL;
+    *out = nullptr;
+    if (!finite_array(U, n * rank) || !finite_array(W, n * rank))
+        return PHICOMB_EINVAL;
+    if (current_device() < 0)
+        return PHICOMB_EDEVICE;
+    phicomb_op op = new_op();
+    if (!op)
+        return PHICOMB_ENOMEM;
+    const size_t bytes = sizeof(double) * (size_t)n * (size_t)rank;
+    const size_t off_w = (bytes + 255) & ~(size_t)255;
+    char *mem = nullptr;
+    if (hipMalloc(&mem, off_w + bytes) != hipSuccess) {
+        free_op(op);
+        return PHICOMB_ENOMEM;
+    }
+    op->mem = mem;
+    if (hipMemcpy(mem, U, bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mem + off_w, W, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        free_op(op);
+        return PHICOMB_EDEVICE;
+    }
+    // ||U W^T||_inf <= max_i sum_k |U_ik| ||W e_k||_1 (an upper bound is all
+    // that the FP32 range guard needs; the exact row sums cost O(n^2 rank))
+    std::vector<double> w1(rank, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < rank; ++k)
+            w1[k] += std::fabs(W[i * rank + k]);
+    double norm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double sr = 0.0;
+        for (int k = 0; k < rank; ++k)
+            sr += std::fabs(U[i * rank + k]) * w1[k];
+        norm = std::max(norm, sr);
+    }
+    op->norm_inf = norm;
+    op->nnz = 2 * n * rank;
+    op->dev.kind = kLowRank;
+    op->dev.n = n;
+    op->dev.rank = rank;
+    op->dev.lr_u = (const double *)mem;
+    op->dev.lr_w = (const double *)(mem + off_w);
+    *out = op;
+    return PHICOMB_OK;
+}
+
 int phicomb_op_destroy(phicomb_op op) {
     if (!op)
         return PHICOMB_EINVAL;
@@ -309,7 +358,7 @@ int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r, cons
     if (precision != PHICOMB_FP64 && precision != PHICOMB_MIXED)
         return PHICOMB_EINVAL;
     std::lock_guard<std::mutex> g(op->mu);
-    const size_t need = solve_workspace_bytes(op->dev.n, p, r, precision);
+    const size_t need = solve_workspace_bytes(op->dev.n, p, r, precision, op_lr_rank(op));
     int st = ensure_workspace(op, need);
     if (st != PHICOMB_OK)
         return st;

@@ -23,7 +23,10 @@ constexpr int kRMax = PHICOMB_MAX_R;          // r <= 4
 constexpr int kTermCap = 150;                 // Taylor terms per loop
 constexpr long kSpinLimit = 1L << 27;         // barrier wait bound (~10 s), then EDEVICE
 
-enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2, kCsrCached = 3 };
+enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2, kCsrCached = 3, kLowRank = 4 };
+
+// Low-rank operators A = U W^T: rank at most kLrRankMax.
+constexpr int kLrRankMax = 16;
 constexpr int kCacheNnz = 8;   // CSR rows up to this length can live in registers
 
 // Operator as seen by the kernels (passed by value).
@@ -40,7 +43,9 @@ struct DevOp {
     const double *val;
     const double *dense;  // row-major n x n
     int max_row_nnz;      // CSR: longest row
-    int pad2;
+    int rank;             // low rank: columns of U and W
+    const double *lr_u;   // low rank: U, row-major n x rank
+    const double *lr_w;   // low rank: W, row-major n x rank
 };
 
 // ------------------------------------------------------------ reductions
@@ -528,7 +533,10 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
               const double *beta, const void *V, double tol, int precision, void *W,
               hipStream_t stream, phicomb_stats_t *stats, void *ws, size_t ws_bytes,
               double *pinned, int cu_floor = 0);
-size_t solve_workspace_bytes(int64_t n, int p, int r, int precision);
+// rank > 0: a low-rank operator of that rank (adds the W^T X exchange area)
+size_t solve_workspace_bytes(int64_t n, int p, int r, int precision, int rank = 0);
+// rank of a low-rank operator, 0 for the other kinds
+inline int op_lr_rank(const phicomb_op_s *op) { return op->dev.kind == kLowRank ? op->dev.rank : 0; }
 // implemented in params.hip
 int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed,
                 hipStream_t stream, phicomb_params_t *out);

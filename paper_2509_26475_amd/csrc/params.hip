@@ -89,6 +89,7 @@ struct ParamsArgs {
     double *basis;      // [m+1][n]
     unsigned *bar;      // sync area
     double *part;       // [2][kPMaxGrid][2]
+    double *lrpart;     // low rank: [2][kLrRankMax][kPMaxGrid] partial W^T x
     double *out;        // 16 values, see params_fp64
 };
 
@@ -112,6 +113,7 @@ template <int KIND>
 __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     __shared__ double wsc[kPNT / 64], wsq[kPNT / 64];
     __shared__ double coef[PHICOMB_MAX_M + 1];
+    __shared__ double lrc[kLrRankMax];
     __shared__ int ok_lds;
     const unsigned G = gridDim.x;
     const int lb = xcd_logical_block(blockIdx.x, G);
@@ -175,6 +177,43 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         ++epoch;
         return tot;
     };
+    // Low rank (A = U W^T, applied as x -> U (W^T x)): lrc = W^T x, each
+    // workgroup's partial over its rows, then the sum over all workgroups in
+    // index order, the same in every workgroup.
+    unsigned lr_epoch = 0;
+    auto lr_dot = [&](const double *x) __attribute__((always_inline)) -> bool {
+        __syncthreads();   // this workgroup's rows of x are written
+        double *pt = P.lrpart + (size_t)(lr_epoch & 1) * kLrRankMax * kPMaxGrid;
+        const int rank = A.rank;
+        for (int k = wave; k < rank; k += kPNT / 64) {
+            double acc = 0.0;
+            for (int64_t row = lo + lane; row < hi; row += 64)
+                acc += A.lr_w[row * rank + k] * x[row];
+            acc = wave_sum(acc);
+            if (lane == 0)
+                pt[(size_t)k * kPMaxGrid + blockIdx.x] = acc;
+        }
+        if (!grid_sync(gs, &ok_lds))
+            return false;
+        for (int k = wave; k < rank; k += kPNT / 64) {
+            double acc = 0.0;
+            for (unsigned b = lane; b < G; b += 64)
+                acc += pt[(size_t)k * kPMaxGrid + b];
+            acc = wave_sum(acc);
+            if (lane == 0)
+                lrc[k] = acc;
+        }
+        __syncthreads();
+        ++lr_epoch;
+        return true;
+    };
+    auto lr_row = [&](int64_t row) __attribute__((always_inline)) -> double {
+        const double *ur = A.lr_u + row * A.rank;
+        double y = 0.0;
+        for (int k = 0; k < A.rank; ++k)
+            y += ur[k] * lrc[k];
+        return y;
+    };
 
     // ---- V_0 = v / ||v||
     if (!P.have_v)
@@ -205,7 +244,18 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         const double *x = col(k - 1);
         double *y = col(k);
         Ssq acc{0.0, 0.0};
-        if constexpr (KIND == kDense) {
+        if constexpr (KIND == kLowRank) {
+            if (!lr_dot(x)) {
+                finish(PHICOMB_EDEVICE, 0, 0, 0, 0, 0, 0, 0);
+                return;
+            }
+            for (int64_t row = lo + tid; row < hi; row += kPNT) {
+                const double w = lr_row(row);
+                const double val = (k == 1) ? w / nv : w;   // A (v/||v||)
+                y[row] = val;
+                ssq_add(acc, val);
+            }
+        } else if constexpr (KIND == kDense) {
             // dense rows: one wave per row, lanes across the row, wave sum
             for (int64_t row = lo + (tid >> 6); row < hi; row += kPNT / 64) {
                 const double *arow = A.dense + row * n;
@@ -281,13 +331,17 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
             v[row] = v[row] * sc;
     }
     for (int k = r + 1; k <= m; ++k) {
-        if (!grid_sync(gs, &ok_lds)) {
+        const double *x = col(k - 1);
+        double *y = col(k);
+        // low rank: only this workgroup's rows of x are read, after lr_dot's barrier
+        if (!(KIND == kLowRank ? lr_dot(x) : grid_sync(gs, &ok_lds))) {
             finish(PHICOMB_EDEVICE, r, s0, 0, 0, 0, 0, 0);
             return;
         }
-        const double *x = col(k - 1);
-        double *y = col(k);
-        if constexpr (KIND == kDense) {
+        if constexpr (KIND == kLowRank) {
+            for (int64_t row = lo + tid; row < hi; row += kPNT)
+                y[row] = lr_row(row) / s0;
+        } else if constexpr (KIND == kDense) {
             for (int64_t row = lo + (tid >> 6); row < hi; row += kPNT / 64) {
                 const double *arow = A.dense + row * n;
                 double sum = 0.0;
@@ -411,16 +465,23 @@ double binom_double(int m, int k) {
     return (double)b;
 }
 
+const void *params_fn(int kind) {
+    switch (kind) {
+    case kStencil: return (const void *)params_kernel<kStencil>;
+    case kDense: return (const void *)params_kernel<kDense>;
+    case kLowRank: return (const void *)params_kernel<kLowRank>;
+    default: return (const void *)params_kernel<kCsr>;
+    }
+}
+
 int max_params_grid(int kind, int device) {
     static std::mutex mu;
-    static int cached[3][64] = {};
+    static int cached[4][64] = {};
     std::lock_guard<std::mutex> g(mu);
-    int &c = cached[kind == kStencil ? 0 : kind == kDense ? 2 : 1][device & 63];
+    int &c = cached[kind == kStencil ? 0 : kind == kDense ? 2 : kind == kLowRank ? 3 : 1][device & 63];
     if (c > 0)
         return c;
-    const void *fn = (kind == kStencil) ? (const void *)params_kernel<kStencil>
-                     : (kind == kDense) ? (const void *)params_kernel<kDense>
-                                        : (const void *)params_kernel<kCsr>;
+    const void *fn = params_fn(kind);
     int per_cu = 0;
     hipDeviceProp_t prop;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPNT, 0) != hipSuccess ||
@@ -439,7 +500,8 @@ constexpr int kBrentMaxIt = 100;
 
 size_t params_workspace_bytes(int64_t n, int m) {
     return (size_t)kSyncBytes + sizeof(double) * (4 * kPMaxGrid + 32 + 128) +
-           sizeof(double) * (size_t)n * (size_t)(m + 1);
+           sizeof(double) * (size_t)n * (size_t)(m + 1) +
+           sizeof(double) * 2 * kLrRankMax * kPMaxGrid;
 }
 
 int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed,
@@ -476,6 +538,7 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     double *bin_dev = a.part + 4 * kPMaxGrid + 16;
     a.binom = bin_dev;
     a.basis = (double *)(base + kSyncBytes + sizeof(double) * (4 * kPMaxGrid + 32 + 128));
+    a.lrpart = a.basis + (size_t)n * (size_t)(m + 1);
     double bin_host[PHICOMB_MAX_M + 1];
     for (int k = 0; k <= m; ++k)
         bin_host[k] = binom_double(m, k);
@@ -492,9 +555,7 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     const int64_t rows_per_wg = (op->dev.kind == kDense) ? 16 : kPNT;
     const int64_t G = std::min<int64_t>(maxg, (n + rows_per_wg - 1) / rows_per_wg);
     const int held = round_xcd(G);   // at most ceil(G/8) of the grid lands on any XCD
-    const void *fn = (op->dev.kind == kStencil) ? (const void *)params_kernel<kStencil>
-                     : (op->dev.kind == kDense) ? (const void *)params_kernel<kDense>
-                                                : (const void *)params_kernel<kCsr>;
+    const void *fn = params_fn(op->dev.kind);
     if (cu_acquire(op->device, held, held) != held)
         return PHICOMB_EDEVICE;
     struct Hold {

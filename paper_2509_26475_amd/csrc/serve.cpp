@@ -119,7 +119,8 @@ class Server {
             }
             q->state.store(1);
             int st = ok ? PHICOMB_OK : PHICOMB_EDEVICE;
-            const size_t need = solve_workspace_bytes(q->op->dev.n, q->p, q->r, q->precision);
+            const size_t need = solve_workspace_bytes(q->op->dev.n, q->p, q->r, q->precision,
+                                                      op_lr_rank(q->op));
             if (st == PHICOMB_OK && w.ws_bytes < need) {
                 if (w.ws)
                     hipFree(w.ws);
@@ -210,7 +211,8 @@ int phicomb_submit(phicomb_op op, const phicomb_params_t *prm, int p, int r, con
     q->V = V;
     q->W = W;
     q->tol = tol;
-    q->bytes = phicomb_request_bytes(op->dev.n, p, r, precision);
+    q->bytes = (int64_t)solve_workspace_bytes(op->dev.n, p, r, precision, op_lr_rank(op)) +
+               8 * op->dev.n * (p + 1 + r);
     const int st = Server::get().submit(q);
     if (st != PHICOMB_OK) {
         delete q;

@@ -17,50 +17,9 @@ __global__ void solve_sync_init(unsigned *bar, int *info) {
         info[threadIdx.x] = 0;
 }
 
-template <int KIND, int R, int RPT, bool EMEM, bool MIX>
-__global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
-    __shared__ SolveShared sh;
-    solve_body<KIND, R, RPT, EMEM, MIX>(P, sh, gridDim.x, blockIdx.x,
-                                        xcd_logical_block(blockIdx.x, gridDim.x));
-}
-
-// ---------------------------------------------------------------- host side
-using KernelFn = void (*)(SolveArgs);
-
-// Instantiated variants: rows per thread 1..8 (register-cached CSR rows:
-// 1..4); larger counts spill and are served by the E-in-memory variant.
-// Mixed-precision variants exist for E in registers with 1..4 rows per
-// thread and for E in memory; other shapes run the FP64 kernel.
-template <int KIND, int R>
-static KernelFn pick_rpt(int rpt, bool emem, bool mix) {
-    if constexpr (KIND != kCsrCached) {
-        if (emem)
-            return mix ? solve_kernel<KIND, R, 1, true, true> : solve_kernel<KIND, R, 1, true, false>;
-    }
-    switch (rpt) {
-    case 1: return mix ? solve_kernel<KIND, R, 1, false, true> : solve_kernel<KIND, R, 1, false, false>;
-    case 2: return mix ? solve_kernel<KIND, R, 2, false, true> : solve_kernel<KIND, R, 2, false, false>;
-    case 4: return mix ? solve_kernel<KIND, R, 4, false, true> : solve_kernel<KIND, R, 4, false, false>;
-    case 8:
-        if constexpr (KIND != kCsrCached)
-            return mix ? nullptr : solve_kernel<KIND, R, 8, false, false>;
-        return nullptr;
-    default: return nullptr;
-    }
-}
-
-template <int KIND>
-static KernelFn pick_r(int r, int rpt, bool emem, bool mix) {
-    switch (r) {
-    case 1: return pick_rpt<KIND, 1>(rpt, emem, mix);
-    case 2: return pick_rpt<KIND, 2>(rpt, emem, mix);
-    case 3: return pick_rpt<KIND, 3>(rpt, emem, mix);
-    case 4: return pick_rpt<KIND, 4>(rpt, emem, mix);
-    default: return nullptr;
-    }
-}
-
 static KernelFn pick_kernel(int kind, int r, int rpt, bool emem, bool mix) {
+    if (kind == kLowRank)
+        return pick_lowrank(r, rpt, emem, mix);
     if (kind == kStencil)
         return pick_r<kStencil>(r, rpt, emem, mix);
     if (kind == kCsr)
@@ -92,25 +51,33 @@ static int max_coresident(KernelFn fn, int device) {
 static size_t sync_bytes() { return (size_t)kSyncBytes + sizeof(double) * 4 * kMaxGrid + 256; }
 size_t solve_sync_bytes() { return sync_bytes(); }
 
-size_t solve_workspace_bytes(int64_t n, int p, int r, int precision) {
+// Entries of W^T X exchanged per term for a low-rank operator: the S-series
+// passes carry the term block and S_0, the recovery passes the 2r columns of F.
+static int64_t lr_values(int p, int r, int rank) {
+    return (int64_t)rank * std::max<int64_t>((int64_t)(p + 1) * r + r, 2LL * r);
+}
+
+size_t solve_workspace_bytes(int64_t n, int p, int r, int precision, int rank) {
     const int64_t cS = (int64_t)(p + 1) * r, cR = 2LL * r, cW = std::max(cS, cR);
     const size_t f32 = (precision == PHICOMB_MIXED) ? (size_t)4 * n * 2 * cR + 256 : 0;
-    return sync_bytes() + (size_t)8 * (size_t)n * (size_t)(cS + 2 * cW + cR) + f32;
+    const size_t lr = (rank > 0) ? (size_t)8 * 2 * lr_values(p, r, rank) * kMaxGrid + 256 : 0;
+    return sync_bytes() + (size_t)8 * (size_t)n * (size_t)(cS + 2 * cW + cR) + f32 + lr;
 }
 
 // Algorithmic bytes of one solve (FP64): every Taylor term reads and writes
 // its term block and its partial-sum block; the S-series terms also read V;
-// the operator is read once per product (CSR arrays; stencil weights are
-// in registers).
+// the operator is read once per product (CSR arrays, the dense matrix, or U
+// and W of a low-rank operator; stencil weights are in registers).
 // Mixed precision: an FP32 term reads and writes its term block in 4-byte
 // words (8 n c bytes fewer per term).
 static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, int r,
                                 int terms_S, int terms_rec, int s_int, int f32_rec) {
     const double w = 8.0, N = (double)n;
     const double cS = (double)(p + 1) * r, cR = 2.0 * r;
-    const double opb = (op.kind == kCsr)     ? (12.0 * (double)nnz + 4.0 * (N + 1))
-                       : (op.kind == kDense) ? 8.0 * N * N
-                                             : 0.0;
+    const double opb = (op.kind == kCsr)       ? (12.0 * (double)nnz + 4.0 * (N + 1))
+                       : (op.kind == kDense)   ? 8.0 * N * N
+                       : (op.kind == kLowRank) ? 16.0 * N * op.rank
+                                               : 0.0;
     double b = w * N * (p + 1) + 2 * w * N * cS;                        // V -> S, D
     b += (terms_S - 1) * (4 * w * N * cS + w * N * (p + 1) + opb);     // S-series terms
     b += 3 * w * N * r + opb;                                           // recover exp(tA/s) v0
@@ -247,6 +214,15 @@ int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, c
         float *f = (float *)(((uintptr_t)d + 255) & ~(uintptr_t)255);
         a.Uf0 = f;
         a.Uf1 = f + (size_t)n * a.cR;
+        d = (double *)(a.Uf1 + (size_t)n * a.cR);
+    }
+    const int rank = (op->dev.kind == kLowRank) ? op->dev.rank : 0;
+    if (rank > 0) {
+        const int64_t lv = lr_values(p, r, rank);
+        if (lv > kLrVals)
+            return PHICOMB_EINVAL;
+        a.lrv = (int)lv;
+        a.lrpart = (double *)(((uintptr_t)d + 255) & ~(uintptr_t)255);
     }
     a.mix_tau = tol / (10.0 * 5.9604644775390625e-08);   // u_fp32 = 2^-24
     // FP32 terms stay clear of overflow ((A - xi I) x with |x| <= partial sum)
@@ -255,7 +231,7 @@ int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, c
     a.mix_hi = 1e30 / std::max(1.0, op->norm_inf + std::fabs(prm->shift));
     a.V = (const double *)V;
     a.W = (double *)W;
-    if (solve_workspace_bytes(n, p, r, precision) > ws_bytes)
+    if (solve_workspace_bytes(n, p, r, precision, rank) > ws_bytes)
         return PHICOMB_EINVAL;
 
     return PHICOMB_OK;

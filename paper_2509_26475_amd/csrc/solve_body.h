@@ -23,6 +23,14 @@
 // the maxima of its row sums (block infinity norms), crosses the XCD-grouped
 // grid barrier, and reduces all workgroups' maxima itself, so every thread
 // takes the same stopping decision.
+//
+// Low-rank operators A = U W^T (Sec. 5, third experiment) are applied
+// matrix-free as x -> U (W^T x).  The small matrix W^T X of the block X that
+// the next product needs rides on the same exchange: the pass that writes X
+// also leaves this workgroup's partial sums over its rows, and after the
+// barrier every workgroup adds all workgroups' partials in index order, so
+// each holds the same W^T X; row i of the product is then U_i (W^T X) minus
+// the shift times X_i, from the row's own data only.
 #pragma once
 
 #include <algorithm>
@@ -36,6 +44,7 @@ namespace phc {
 
 constexpr int kNT = 512;           // threads per workgroup of the solve kernel (8 waves)
 constexpr int kMaxGrid = 4096;     // partial-maximum slots per parity
+constexpr int kLrVals = 256;       // entries of W^T X exchanged per term at most
 
 struct SolveArgs {
     DevOp op;
@@ -56,6 +65,8 @@ struct SolveArgs {
     double mix_lo, mix_hi;              // partial-sum norms for which FP32 terms are safe
     unsigned *bar;                      // sync area (kSyncBytes)
     double *part;                       // [2][kMaxGrid][2] partial maxima
+    double *lrpart;                     // low rank: [2][lrv][kMaxGrid] partial W^T X
+    int lrv;                            // low rank: rank * max(cS + r, 2r)
     int *info;                          // status, terms_S, terms_rec, max_terms_step
 };
 
@@ -170,11 +181,53 @@ __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, in
     __syncthreads();
 }
 
+// ------------------------------------------------------- low-rank operator
+// This workgroup's partial sums of W^T X over its rows [lo, hi) for columns
+// c < ncols of X (column-major, leading dimension n), stored value-major at
+// out[(voff + c rank + k) kMaxGrid + bid]: one wave per value, lanes over
+// the rows, a fixed shuffle tree.  The block was written by this workgroup.
+template <class TX>
+__device__ __forceinline__ void lr_publish(const DevOp &A, int64_t n, int64_t lo, int64_t hi,
+                                           const TX *__restrict__ X, int ncols, int voff,
+                                           double *__restrict__ out, unsigned bid) {
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rank = A.rank;
+    for (int v = wave; v < ncols * rank; v += kNT / 64) {
+        const int c = v / rank, k = v % rank;
+        const TX *xc = X + (int64_t)c * n;
+        double acc = 0.0;
+        for (int64_t row = lo + lane; row < hi; row += 64)
+            acc += A.lr_w[row * rank + k] * (double)xc[row];
+        acc = wave_sum(acc);
+        if (lane == 0)
+            out[(size_t)(voff + v) * kMaxGrid + bid] = acc;
+    }
+}
+
+// W^T X = the sum of all G workgroups' partials, in the same order in every
+// workgroup: one wave per value, lanes over the workgroups, a fixed tree.
+__device__ __forceinline__ void lr_gather(const double *__restrict__ part, unsigned G, int nv,
+                                          double *lrc) {
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int v = wave; v < nv; v += kNT / 64) {
+        double acc = 0.0;
+        for (unsigned g = lane; g < G; g += 64)
+            acc += part[(size_t)v * kMaxGrid + g];
+        acc = wave_sum(acc);
+        if (lane == 0)
+            lrc[v] = acc;
+    }
+    __syncthreads();
+}
+
 // Workgroup-shared state of one solve.
 struct SolveShared {
     double Mk[kRMax][kPMax1][kPMax1];   // J_step^(k-1) / k!
     double Cj[kRMax][kPMax1][kPMax1];   // gam[i][b] * Mk[i][b][.]
     double red[kNT / 64][2];
+    double lrc[kLrVals];                // low rank: W^T X of the coming product
     int ok;
 };
 
@@ -225,6 +278,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             load_cached_row(A, row, crow[decltype(q)::value]);
         });
+    int lr_off = 0;   // low rank: column of W^T X holding the operand's first column
     DenseShared *dsp = nullptr;
     if constexpr (KIND == kDense) {
         __shared__ DenseShared dense_lds;
@@ -247,6 +301,20 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
 #pragma unroll
             for (int j = 0; j < NC; ++j)
                 y[j] = (TA)dsp->Y[row - lo][col0 + j];
+        } else if constexpr (KIND == kLowRank) {
+            // U_row (W^T X) - shift X_row, W^T X gathered at the last exchange
+            const int rank = A.rank;
+            const double *ur = A.lr_u + row * rank;
+            const double *cw = sh.lrc + (lr_off + col0) * rank;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                y[j] = -(TA)shift * (TA)X[(int64_t)(col0 + j) * n + row];
+            for (int k = 0; k < rank; ++k) {
+                const TA u = (TA)ur[k];
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+                    y[j] += u * (TA)cw[j * rank + k];
+            }
         } else if constexpr (CACHED) {
             apply_cached<NC, TX, TA>(crow[decltype(q)::value], (unsigned)row, X, n, col0, shift,
                                      y);
@@ -265,12 +333,25 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         return;
     }
     unsigned epoch = 0;
+    // low rank: partial W^T X of a block this workgroup just wrote, for the
+    // coming exchange (nlr values in all)
+    int nlr = 0;
+    auto lr_part = [&]() { return P.lrpart + (size_t)(epoch & 1) * P.lrv * kMaxGrid; };
+    auto publish = [&](const auto *X, int ncols, int voff) __attribute__((always_inline)) {
+        if constexpr (KIND == kLowRank) {
+            lr_publish(A, n, lo, hi, X, ncols, voff, lr_part(), single ? 0u : bid);
+            nlr = voff + ncols * A.rank;
+        }
+    };
     // publish this workgroup's maxima, cross the barrier, reduce all of them
     auto exchange = [&](auto &v) __attribute__((always_inline)) -> bool {
         constexpr int NV = std::extent<std::remove_reference_t<decltype(v)>>::value;
         if (single) {
             wait_own_stores();
             workgroup_max<NV, kNT>(v, red);
+            if constexpr (KIND == kLowRank)
+                lr_gather(lr_part(), 1, nlr, sh.lrc);
+            ++epoch;
             return true;
         }
         double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
@@ -278,6 +359,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         if (!grid_sync(gs, &sh.ok))
             return false;
         load_partials<NV, kNT>(pt, G, v, red);
+        if constexpr (KIND == kLowRank)
+            lr_gather(lr_part(), G, nlr, sh.lrc);
         ++epoch;
         return true;
     };
@@ -304,6 +387,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         }
         nrm[0] = nmax(nrm[0], su);
     });
+    publish(P.U0, P.cS, 0);
+    publish(P.S, R, P.cS * A.rank);   // S_0: operand of the first recovery product
     nrm[1] = nrm[0];
     if (!exchange(nrm)) {
         finish(PHICOMB_EDEVICE, 0, 0, 0);
@@ -381,6 +466,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             mx[0] = nmax(mx[0], su);
             mx[1] = nmax(mx[1], ss);
         });
+        publish(Un, P.cS, 0);
+        publish(P.S, R, P.cS * A.rank);
         if (!exchange(mx)) {
             finish(PHICOMB_EDEVICE, k, 0, 0);
             return;
@@ -403,6 +490,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     {
         double mx[1] = {0.0};
         dense_pass(P.S, R, 0.0);
+        lr_off = P.cS;
         for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
             double y[R];
             opr(row, q, P.S, 0, 0.0, y);
@@ -438,6 +526,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             finish(PHICOMB_OK, terms_S, 0, 0);
             return;
         }
+        lr_off = 0;
+        publish(P.U0, 2 * R, 0);
         if (!exchange(mx)) {
             finish(PHICOMB_EDEVICE, terms_S, 0, 0);
             return;
@@ -509,6 +599,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                 mx[0] = nmax(mx[0], sf);
                 mx[1] = nmax(mx[1], se);
             });
+            if (MIX && t32)
+                publish(Fn32, 2 * R, 0);
+            else
+                publish(Fn, 2 * R, 0);
             if (!exchange(mx)) {
                 finish(PHICOMB_EDEVICE, terms_S, tot + kk, maxstep);
                 return;
@@ -569,6 +663,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         });
         if (last)
             break;
+        publish(Fx, 2 * R, 0);
         if (!exchange(mx)) {
             finish(PHICOMB_EDEVICE, terms_S, tot, maxstep);
             return;
@@ -577,6 +672,52 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     }
     finish(status, terms_S, tot, maxstep);
 }
+
+// ------------------------------------------------------------ single solve
+template <int KIND, int R, int RPT, bool EMEM, bool MIX>
+__global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
+    __shared__ SolveShared sh;
+    solve_body<KIND, R, RPT, EMEM, MIX>(P, sh, gridDim.x, blockIdx.x,
+                                        xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+using KernelFn = void (*)(SolveArgs);
+
+// Instantiated variants: rows per thread 1..8 (register-cached CSR rows:
+// 1..4); larger counts spill and are served by the E-in-memory variant.
+// Mixed-precision variants exist for E in registers with 1..4 rows per
+// thread and for E in memory; other shapes run the FP64 kernel.
+template <int KIND, int R>
+KernelFn pick_rpt(int rpt, bool emem, bool mix) {
+    if constexpr (KIND != kCsrCached) {
+        if (emem)
+            return mix ? solve_kernel<KIND, R, 1, true, true> : solve_kernel<KIND, R, 1, true, false>;
+    }
+    switch (rpt) {
+    case 1: return mix ? solve_kernel<KIND, R, 1, false, true> : solve_kernel<KIND, R, 1, false, false>;
+    case 2: return mix ? solve_kernel<KIND, R, 2, false, true> : solve_kernel<KIND, R, 2, false, false>;
+    case 4: return mix ? solve_kernel<KIND, R, 4, false, true> : solve_kernel<KIND, R, 4, false, false>;
+    case 8:
+        if constexpr (KIND != kCsrCached)
+            return mix ? nullptr : solve_kernel<KIND, R, 8, false, false>;
+        return nullptr;
+    default: return nullptr;
+    }
+}
+
+template <int KIND>
+KernelFn pick_r(int r, int rpt, bool emem, bool mix) {
+    switch (r) {
+    case 1: return pick_rpt<KIND, 1>(rpt, emem, mix);
+    case 2: return pick_rpt<KIND, 2>(rpt, emem, mix);
+    case 3: return pick_rpt<KIND, 3>(rpt, emem, mix);
+    case 4: return pick_rpt<KIND, 4>(rpt, emem, mix);
+    default: return nullptr;
+    }
+}
+
+// Low-rank variants (instantiated in solve_lowrank.hip).
+KernelFn pick_lowrank(int r, int rpt, bool emem, bool mix);
 
 // ---------------------------------------------------------------- host side
 // (implemented in solve.hip)
