@@ -249,3 +249,62 @@ def full(problem, m: int = 61, form: str = "beta", kcap: int = KCAP, prm: Option
     W, st = solve(o, problem.p, problem.r, problem.t, problem.beta, problem.V, problem.tol,
                   prm["shift"], prm["s"], form=form, alpha=problem.alpha, kcap=kcap)
     return W, st, prm
+
+
+# ------------------------------------------------------------ expRK4s6
+# Nodes of the fourth-order six-stage exponential Runge-Kutta scheme
+# (Sec. 1, eq. (expRK4s6)).
+EXPRK_C = {2: 0.5, 3: 0.5, 4: 1.0 / 3.0, 5: 5.0 / 6.0, 6: 1.0 / 3.0}
+
+
+def _cubic(gc, u):
+    """Pointwise reaction g(u) = gc[0] + gc[1] u + gc[2] u^2 + gc[3] u^3."""
+    return gc[0] + u * (gc[1] + u * (gc[2] + u * gc[3]))
+
+
+def exprk4s6(op, gc, u0: np.ndarray, h: float, nsteps: int, tol: float, shift: float,
+             s: float):
+    """u' = A u + g(u) over nsteps steps of size h with the scheme of Sec. 1,
+    eq. (expRK4s6), every phi-combination evaluated by Algorithm 3 with the
+    parameters (shift, s) of Algorithm 1 reused for all calls.  The stages
+    that the scheme allows to be computed together are one block call each
+    (Sec. 5, fourth experiment): U2; {U3, U4}; {U5, U6}; u_{n+1}.  Every
+    call has v_0 = 0 and v_1 = h f(u_n).  Returns (u, per-call stats)."""
+    o = _as_op(op)
+    c = EXPRK_C
+    u = np.array(u0, dtype=np.float64)
+    calls = []
+
+    def call(t, beta, cols):
+        V = np.stack([np.zeros_like(u)] + cols, axis=1)
+        W, st = solve(o, V.shape[1] - 1, len(t), np.asarray(t), np.asarray(beta), V, tol,
+                      shift, s)
+        calls.append(st)
+        return W
+
+    for _ in range(nsteps):
+        gu = _cubic(gc, u)
+        f = apply(o, u) + gu
+        hf = h * f
+        # U2 = u + phi_1(c2 h A) c2 h f
+        W = call([c[2] * h], [[0.0, c[2]]], [hf])
+        D2 = _cubic(gc, u + W[:, 0]) - gu
+        # U_k = u + phi_1(c_k h A) c_k h f + phi_2(c_k h A) (c_k^2/c2) h D2, k = 3, 4
+        W = call([c[3] * h, c[4] * h],
+                 [[0.0, c[k], c[k] ** 2 / c[2]] for k in (3, 4)], [hf, h * D2])
+        D3 = _cubic(gc, u + W[:, 0]) - gu
+        D4 = _cubic(gc, u + W[:, 1]) - gu
+        # U_j, j = 5, 6: phi_2 weight c_j^2/(c3-c4), phi_3 weight 2 c_j^3/(c3-c4)
+        q2 = h * (-(c[4] / c[3]) * D3 + (c[3] / c[4]) * D4)
+        q3 = h * (D3 / c[3] - D4 / c[4])
+        W = call([c[5] * h, c[6] * h],
+                 [[0.0, c[j], c[j] ** 2 / (c[3] - c[4]), 2.0 * c[j] ** 3 / (c[3] - c[4])]
+                  for j in (5, 6)], [hf, q2, q3])
+        D5 = _cubic(gc, u + W[:, 0]) - gu
+        D6 = _cubic(gc, u + W[:, 1]) - gu
+        # u_{n+1}: phi_2 weight 1/(c5-c6), phi_3 weight 2/(c5-c6)
+        q2 = h * (-(c[6] / c[5]) * D5 + (c[5] / c[6]) * D6)
+        q3 = h * (D5 / c[5] - D6 / c[6])
+        W = call([h], [[0.0, 1.0, 1.0 / (c[5] - c[6]), 2.0 / (c[5] - c[6])]], [hf, q2, q3])
+        u = u + W[:, 0]
+    return u, calls

@@ -265,3 +265,21 @@ def rel2_cols(a, b) -> np.ndarray:
     a = np.asarray(a).reshape(b.shape[0], -1)
     b = np.asarray(b).reshape(b.shape[0], -1)
     return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+def ode_reference(op, gc, u0, t_end: float, rtol: float = 1e-12):
+    """u(t_end) of u' = A u + g(u) (g the cubic with coefficients gc) by
+    scipy's explicit Runge-Kutta DOP853 at rtol = atol (the paper's fourth
+    experiment uses a stiff solver at 1e-12 for its reference)."""
+    from scipy.integrate import solve_ivp
+    import scipy.sparse as sp
+    rp, ci, va = op.csr()
+    A = sp.csr_matrix((va, ci, rp), shape=(op.n, op.n))
+
+    def rhs(_t, u):
+        return A @ u + (gc[0] + u * (gc[1] + u * (gc[2] + u * gc[3])))
+
+    sol = solve_ivp(rhs, (0.0, t_end), np.asarray(u0, dtype=np.float64), method="DOP853",
+                    rtol=rtol, atol=rtol, t_eval=[t_end])
+    assert sol.success, sol.message
+    return sol.y[:, -1]

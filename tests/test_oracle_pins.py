@@ -513,3 +513,59 @@ def test_third_experiment_within_tables2to4_envelope(orc, core):
             assert st2["s_int"] > st["s_int"]
             err = refs.rel1_cols(Wo, ref[:, None])[0]
         assert err <= bar, (core, t, err, e)
+
+
+# ------------------------------------------- fourth experiment (expRK4s6, ADR)
+def test_adr_operator_second_order():
+    """The ADR operator of the fourth experiment applied to the grid values of
+    u = cos(pi x/2) cos(pi y/2) (zero slope at x = 0 and y = 0, zero at x = 1
+    and y = 1) approaches eps Lap u - alpha (u_x + u_y) at second order."""
+    eps, alpha = 1e-3, -0.5
+    errs = []
+    for N in (20, 40, 80):
+        x = np.arange(N) / N
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        cx, cy = np.cos(np.pi * X / 2), np.cos(np.pi * Y / 2)
+        sx, sy = np.sin(np.pi * X / 2), np.sin(np.pi * Y / 2)
+        u = (cx * cy).ravel()
+        Lu = (eps * (-(np.pi ** 2) / 2) * cx * cy
+              - alpha * (-(np.pi / 2) * sx * cy - (np.pi / 2) * cx * sy)).ravel()
+        op = wl.adr_operator(N, eps, alpha)
+        errs.append(np.abs(op.dense() @ u - Lu).max())
+    assert 3.2 < errs[0] / errs[1] < 4.8 and 3.2 < errs[1] / errs[2] < 4.8, errs
+
+
+def test_exprk4s6_fourth_order(orc):
+    """expRK4s6 (Sec. 1, eq. (expRK4s6)) on the ADR problem at N = 10 with a
+    milder reaction (gamma = 20) to t = 1/2 converges at order four against a
+    1e-12 Runge-Kutta reference: halving h divides the error by about 16.  A
+    wrong stage weight or node drops the order."""
+    N, T = 10, 0.5
+    op = wl.adr_operator(N)
+    gc = wl.adr_reaction(20.0)
+    u0 = wl.adr_initial(N)
+    ref = refs.ode_reference(op, gc, u0, T)
+    o = orc.Operator(op)
+    prm = orc.params(o, 1e-14, wl.params_vector(op.n))
+    errs = []
+    for ns in (16, 32, 64):
+        u, calls = orc.exprk4s6(o, gc, u0, T / ns, ns, 1e-14, prm["shift"], prm["s"])
+        assert len(calls) == 4 * ns
+        errs.append(np.abs(u - ref).max() / np.abs(ref).max())
+    assert 12 < errs[0] / errs[1] < 20 and 12 < errs[1] / errs[2] < 20, errs
+
+
+def test_exprk4s6_linear_problem_is_exponential(orc):
+    """With g = 0 every stage and the update are exact phi-combinations, so the
+    scheme returns e^(T A) u0 up to the solver tolerance."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import expm_multiply
+    N, T, ns = 10, 0.5, 8
+    op = wl.adr_operator(N)
+    u0 = wl.adr_initial(N)
+    o = orc.Operator(op)
+    prm = orc.params(o, 1e-14, wl.params_vector(op.n))
+    u, _ = orc.exprk4s6(o, np.zeros(4), u0, T / ns, ns, 1e-14, prm["shift"], prm["s"])
+    rp, ci, va = op.csr()
+    ref = expm_multiply(T * sp.csr_matrix((va, ci, rp), shape=(op.n, op.n)), u0)
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()

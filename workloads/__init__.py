@@ -34,7 +34,8 @@ __all__ = [
     "laplacian_3d", "convdiff_2d_upwind", "dense_upper_nonnormal",
     "config1", "config2", "config3", "config4", "config5_stream",
     "small_problem", "params_vector", "LowRank", "dct2_basis", "lowrank_cores",
-    "lowrank_operator", "exp3_problem", "EXP3_SHAPES",
+    "lowrank_operator", "exp3_problem", "EXP3_SHAPES", "ADR", "adr_operator",
+    "adr_initial", "adr_reaction", "adr_steps",
 ]
 
 
@@ -347,6 +348,65 @@ def exp3_problem(core_name: str, t: float, n: Optional[int] = None, seed: int = 
     ta = np.array([float(t)])
     return Problem(f"exp3_{core_name}_n{n}_t{t:g}", op, p, 1, ta, np.ones((1, p + 1)),
                    _V_normal(n, p, seed), 2.0 ** -53, params_vector(n, 1), np.ones(1))
+
+
+# Fourth experiment of Sec. 5: 2-D advection-diffusion-reaction
+#   u_t = eps Lap u - alpha (u_x + u_y) + gamma u (u - 1/2)(1 - u)  on [0,1]^2,
+# homogeneous Neumann on x = 0 and y = 0, homogeneous Dirichlet on x = 1 and
+# y = 1, u(0) = 256 x^2 y^2 (1-x)^2 (1-y)^2, t in [0, 1/2].
+ADR = {"eps": 1e-3, "alpha": -0.5, "gamma": 1000.0, "t_end": 0.5, "N": 100}
+
+
+def adr_operator(N: int = 100, eps: float = 1e-3, alpha: float = -0.5) -> CSR:
+    """Second-order finite differences of eps Lap - alpha (d/dx + d/dy) on the
+    N x N unknowns x_i = i/N, i = 0..N-1 (x = 1 is the Dirichlet boundary and
+    carries no unknown), the same in y, grid index i + N j.  The Neumann
+    condition at x = 0 (y = 0) is imposed with the mirrored ghost value
+    u_{-1} = u_1: the diffusion row becomes (2 u_1 - 2 u_0)/h^2 and the
+    central advection difference vanishes there."""
+    h = 1.0 / N
+    d2 = eps / h ** 2
+    d1 = -alpha / (2.0 * h)        # coefficient of (u_{i+1} - u_{i-1})
+    rows, cols, vals = [], [], []
+    for j in range(N):
+        for i in range(N):
+            k = i + N * j
+            ent = {k: -4.0 * d2}
+            for (ii, jj, axis) in ((i, j, 0), (j, i, 1)):
+                step = 1 if axis == 0 else N
+                if ii == 0:              # mirrored ghost: u_{-1} = u_1
+                    ent[k + step] = ent.get(k + step, 0.0) + 2.0 * d2
+                else:
+                    ent[k - step] = ent.get(k - step, 0.0) + d2 - d1
+                    if ii < N - 1:
+                        ent[k + step] = ent.get(k + step, 0.0) + d2 + d1
+            for c in sorted(ent):
+                rows.append(k)
+                cols.append(c)
+                vals.append(ent[c])
+    rows = np.asarray(rows)
+    rp = np.zeros(N * N + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    return CSR(N * N, rp, np.asarray(cols, dtype=np.int32), np.asarray(vals, dtype=np.float64))
+
+
+def adr_initial(N: int = 100) -> np.ndarray:
+    x = np.arange(N) / N
+    X, Y = np.meshgrid(x, x, indexing="xy")      # X varies along the fast index
+    return np.ascontiguousarray((256.0 * X ** 2 * Y ** 2 * (1 - X) ** 2 * (1 - Y) ** 2).ravel())
+
+
+def adr_reaction(gamma: float = 1000.0) -> np.ndarray:
+    """g(u) = gamma u (u - 1/2)(1 - u) as cubic coefficients c0 + c1 u + c2 u^2 + c3 u^3."""
+    return np.array([0.0, -0.5 * gamma, 1.5 * gamma, -gamma])
+
+
+def adr_steps(i: int) -> tuple:
+    """Step size h_i = 2^-8 (t_end - t0)/(i + 1), i = 1..7, and the number
+    of steps that reach t_end."""
+    nsteps = 256 * (i + 1)
+    return ADR["t_end"] / nsteps, nsteps
 
 
 def config4(count: int = 256, seed: int = 0, side_range=(32, 256)) -> List[Problem]:
