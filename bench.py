@@ -214,6 +214,41 @@ def bench_exp3(pc, wl, torch) -> dict:
     return out
 
 
+def bench_exp4(pc, wl, torch) -> dict:
+    """Fourth experiment of the paper: expRK4s6 on the 2-D ADR problem (N = 100,
+    n = 10^4) to t = 1/2 with h_i = 2^-8 (1/2)/(i + 1), i = 1..7, tol 1e-7;
+    device time of each whole integration (4 block calls per step) and its
+    relative max-norm error against a 1e-12 Runge-Kutta reference."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    import refs
+    op = wl.adr_operator(wl.ADR["N"])
+    gc = wl.adr_reaction(wl.ADR["gamma"])
+    u0 = wl.adr_initial(wl.ADR["N"])
+    ref = refs.ode_reference(op, gc, u0, wl.ADR["t_end"])
+    H = pc.Operator(op)
+    prm = pc.phicomb_params(H.h, 1e-7, 61, None, 1)
+    out = {"workload": "ADR 2-D, N=100 (n=1e4), eps=1e-3, alpha=-1/2, gamma=1000, t in [0, 1/2], "
+                       "expRK4s6, tol 1e-7",
+           "h": [], "steps": [], "ms": [], "rel_err_inf": [], "calls": []}
+    for i in range(1, 8):
+        h, ns = wl.adr_steps(i)
+        u = torch.from_numpy(u0.copy()).cuda()
+        torch.cuda.synchronize()
+        st = pc.phicomb_exprk4s6(H.h, prm, gc, h, ns, 1e-7, pc.FP64, u)
+        torch.cuda.synchronize()
+        err = float(np.abs(u.cpu().numpy() - ref).max() / np.abs(ref).max())
+        print(f"[bench] fourth experiment h_{i}: {ns} steps {st.ms:.0f} ms err {err:.2e}",
+              file=sys.stderr, flush=True)
+        out["h"].append(h)
+        out["steps"].append(ns)
+        out["ms"].append(st.ms)
+        out["rel_err_inf"].append(err)
+        out["calls"].append(st.calls)
+    H.close()
+    return out
+
+
 def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
     """Poisson request stream over a resident operator pool (70 % 2-D/3-D
     stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
@@ -411,6 +446,9 @@ def main(argv=None) -> int:
         t1 = time.perf_counter()
         line["exp3"] = bench_exp3(pc, wl, torch)
         progress("third experiment", t1)
+        t1 = time.perf_counter()
+        line["exp4"] = bench_exp4(pc, wl, torch)
+        progress("fourth experiment", t1)
         if args.serve_seconds > 0:
             t1 = time.perf_counter()
             line["served"] = bench_served(pc, wl, torch, args.serve_seconds, args.serve_rate,

@@ -245,6 +245,35 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
 
 int phicomb_batch_destroy(phicomb_batch b);
 
+/* ------------------------------------------------------- exponential integrator
+ * expRK4s6 (Sec. 1, eq. (expRK4s6): Luan's fourth-order six-stage exponential
+ * Runge-Kutta scheme, nodes c2 = c3 = 1/2, c4 = c6 = 1/3, c5 = 5/6) for
+ * u' = A u + g(u) with a pointwise cubic reaction
+ * g(u) = g[0] + g[1] u + g[2] u^2 + g[3] u^3, as in the fourth experiment of
+ * Sec. 5.  nsteps steps of size h advance the device vector u (n FP64,
+ * overwritten in place).  Each step makes four block calls of Algorithm 3,
+ * with the stages the scheme allows to be formed together in one call
+ * (U2; U3 and U4; U5 and U6; u_{n+1}), all with the parameters prm of
+ * Algorithm 1 (computed once for A and tol and reused, Sec. 6); tol and
+ * precision as for phicomb_solve.  The operator must be a stencil, CSR or
+ * dense operator (EINVAL for low rank).  Stage buffers (8 n doubles) stay
+ * with the operator.  Blocking; the first failing call's status is returned
+ * and u then holds the last completed step.  stats may be NULL. */
+typedef struct {
+    int32_t steps;          /* steps completed */
+    int32_t calls;          /* Algorithm 3 calls (4 per step) */
+    int32_t max_s_int;      /* largest scaling count of any call */
+    int32_t status;
+    int64_t terms;          /* Taylor terms over all calls (S-series + recovery) */
+    int64_t fp32_terms;     /* mixed precision: recovery terms evaluated in FP32 */
+    double ms;              /* device time of the whole integration, milliseconds */
+    double kernel_ms;       /* device time of the solve kernels alone */
+} phicomb_exprk_stats_t;
+
+int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, const double g[4], double h,
+                     int nsteps, double tol, int precision, void *u, void *stream,
+                     phicomb_exprk_stats_t *stats);
+
 const char *phicomb_strerror(int status);
 
 #ifdef __cplusplus

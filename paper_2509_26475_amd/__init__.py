@@ -53,6 +53,15 @@ class StatsT(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ExprkStatsT(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("calls", C.c_int32), ("max_s_int", C.c_int32),
+                ("status", C.c_int32), ("terms", C.c_int64), ("fp32_terms", C.c_int64),
+                ("ms", C.c_double), ("kernel_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class BatchItemT(C.Structure):
     _fields_ = [("op", C.c_void_p), ("prm", C.POINTER(ParamsT)), ("p", C.c_int32),
                 ("r", C.c_int32), ("t", C.c_void_p), ("beta", C.c_void_p), ("V", C.c_void_p),
@@ -89,6 +98,7 @@ def _lib():
             "phicomb_batch_run": ([P, P, P], I32),
             "phicomb_batch_info": ([P, P, P, P], I32),
             "phicomb_batch_destroy": ([P], I32),
+            "phicomb_exprk4s6": ([P, P, P, D, I32, D, I32, P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -190,6 +200,23 @@ def phicomb_solve(h, prm: ParamsT, p: int, r: int, t, beta, V, tol: float, preci
                               C.c_void_p(V.data_ptr()), float(tol), int(precision),
                               C.c_void_p(W.data_ptr()), _stream_ptr(stream), C.byref(stats))
     _check(st, "phicomb_solve")
+    return stats
+
+
+def phicomb_exprk4s6(h, prm: ParamsT, g, step: float, nsteps: int, tol: float, precision: int,
+                     u, stream=None) -> ExprkStatsT:
+    """expRK4s6 for u' = A u + g(u), g(u) = g[0] + g[1] u + g[2] u^2 + g[3] u^3;
+    u: torch float64 cuda tensor [n] (or [n][1]), advanced in place."""
+    ga = np.ascontiguousarray(g, dtype=np.float64)
+    if ga.shape != (4,):
+        raise ValueError("g must hold 4 cubic coefficients")
+    uu = u.view(-1, 1) if u.dim() == 1 else u
+    _check_device_tensor(uu, (None, 1), "u")
+    stats = ExprkStatsT()
+    st = _lib().phicomb_exprk4s6(h, C.byref(prm), _np_ptr(ga), float(step), int(nsteps),
+                                 float(tol), int(precision), C.c_void_p(u.data_ptr()),
+                                 _stream_ptr(stream), C.byref(stats))
+    _check(st, "phicomb_exprk4s6")
     return stats
 
 

@@ -43,6 +43,8 @@ void free_op(phicomb_op op) {
         hipFree(op->dense_mem);
     if (op->ws.ptr)
         hipFree(op->ws.ptr);
+    if (op->aux.ptr)
+        hipFree(op->aux.ptr);
     if (op->pinned)
         hipHostFree(op->pinned);
     delete op;

@@ -508,6 +508,7 @@ struct phicomb_op_s {
     void *dense_mem = nullptr;    // dense operators: row-major n x n copy
     std::mutex mu;                // serialises solves on this operator
     phc::Workspace ws;            // grow-only workspace of blocking solves
+    phc::Workspace aux;           // grow-only stage buffers of the time stepper
     double *pinned = nullptr;     // small pinned host buffer for read-backs
 };
 
