@@ -14,6 +14,7 @@ wrapper transposes (a layout change only).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from typing import Optional
@@ -308,3 +309,40 @@ def exprk4s6(op, gc, u0: np.ndarray, h: float, nsteps: int, tol: float, shift: f
         W = call([h], [[0.0, 1.0, 1.0 / (c[5] - c[6]), 2.0 / (c[5] - c[6])]], [hf, q2, q3])
         u = u + W[:, 0]
     return u, calls
+
+
+# ------------------------------------------------ the Proposition's series
+def series_block(op, p: int, r: int, t, beta, V: np.ndarray, tol: float, kcap: int = KCAP):
+    """The single series of the Proposition in Sec. 4 with g_i = phi_i:
+    G = sum_j A^j V D_j Gamma T^j, D_j = diag(1/(i+j)!, i = 0..p), with the
+    Vandermonde Gamma replaced by a general weight table (Gamma[i, k] =
+    beta[k, i]; the proof is unchanged).  Column k of G is
+    w_k = sum_i beta[k, i] phi_i(t_k A) v_i.  No shift and no scaling: terms
+    are added until two consecutive ones are below tol times the block norm
+    (the stopping rule (stopTm) of Algorithm 3, block infinity norm).
+    Returns (W [n][r], stats)."""
+    o = _as_op(op)
+    t = np.asarray(t, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64).reshape(r, p + 1)
+    X = np.array(V, dtype=np.float64)            # A^j V, column i = A^j v_i
+    tj = np.ones(r)                              # t_k^j
+    fact = np.array([float(math.factorial(i)) for i in range(p + 1)])   # (i+j)!
+
+    def term():
+        # column k: sum_i beta[k, i] t_k^j / (i+j)! A^j v_i
+        return X @ (beta / fact[None, :]).T * tj[None, :]
+
+    G = term()
+    c1, c2 = math.inf, np.abs(G).sum(axis=1).max()
+    j = 0
+    while c1 + c2 > tol * np.abs(G).sum(axis=1).max():
+        if j + 1 >= kcap:
+            raise OracleError(-4)
+        j += 1
+        X = np.stack([apply(o, X[:, i]) for i in range(p + 1)], axis=1)
+        tj = tj * t
+        fact = fact * (np.arange(p + 1) + j)
+        T = term()
+        G = G + T
+        c1, c2 = c2, np.abs(T).sum(axis=1).max()
+    return G, {"terms": j + 1}

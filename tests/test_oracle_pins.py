@@ -569,3 +569,44 @@ def test_exprk4s6_linear_problem_is_exponential(orc):
     rp, ci, va = op.csr()
     ref = expm_multiply(T * sp.csr_matrix((va, ci, rp), shape=(op.n, op.n)), u0)
     assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------ the Proposition's block series
+@pytest.mark.parametrize("seed,ts", [(4, 0.5), (5, 0.3), (6, 0.2)])
+def test_series_block_against_augmented_exponential(orc, seed, ts):
+    """The single series of the Proposition (Sec. 4) with g_i = phi_i against
+    the exact augmented exponential (Theorem 1) on small non-normal matrices
+    with |t| ||A||_inf up to about 18 (at 24 the unscaled series already
+    loses a digit to cancellation: 1.2e-13)."""
+    pr = wl.small_problem(7, 3, 3, seed=seed, t_scale=ts)
+    W, st = orc.series_block(pr.op, pr.p, pr.r, pr.t, pr.beta, pr.V, 2.0 ** -53)
+    Wq = refs.exact_dense_q(pr.op.A, pr.t, pr.beta, pr.V)
+    assert refs.rel2(W, Wq) < 1e-14
+
+
+def test_series_block_single_phi_for_many_abscissae(orc):
+    """The Remark after the Proposition: with every v_i zero except v_k the
+    columns are phi_k(t_i A) v_k; on a diagonal operator these are scalar
+    phi_k values (50-digit mpmath)."""
+    lams = np.array([-3.0, -1.0, -0.25, 0.0, 0.5, 1.5])
+    op = _diag_op(lams)
+    k, p = 2, 3
+    t = np.array([0.1, 0.4, 0.7, 1.0])
+    V = np.zeros((len(lams), p + 1))
+    V[:, k] = np.arange(1.0, len(lams) + 1)
+    beta = np.ones((len(t), p + 1))
+    W, _ = orc.series_block(op, p, len(t), t, beta, V, 2.0 ** -53)
+    for c, tc in enumerate(t):
+        ref = np.array([float(refs.phi_mp(k, tc * lam)) for lam in lams]) * V[:, k]
+        assert np.abs(W[:, c] - ref).max() <= 2e-16 * np.abs(ref).max() * 4
+
+
+def test_series_block_agrees_with_algorithm3(orc):
+    """Two different evaluations of the same combinations: the unscaled,
+    unshifted series and Algorithm 3 with Algorithm 1's parameters."""
+    pr = wl.config1()
+    t = pr.t * np.array([1.0])
+    prm = orc.params(pr.op, pr.tol, pr.v)
+    W3, _ = orc.solve(pr.op, pr.p, pr.r, t, pr.beta, pr.V, pr.tol, prm["shift"], prm["s"])
+    Ws, st = orc.series_block(pr.op, pr.p, pr.r, t, pr.beta, pr.V, pr.tol)
+    assert refs.rel2(Ws, W3) < 1e-14
