@@ -245,6 +245,22 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
 
 int phicomb_batch_destroy(phicomb_batch b);
 
+/* The single block series of the Proposition in Sec. 4 with g_i = phi_i:
+ * W[:, k] = sum_i beta[k][i] phi_i(t_k A) v_i evaluated as
+ * sum_j A^j V D_j Gamma T^j (D_j = diag(1/(i+j)!), Gamma[i][k] = beta[k][i]),
+ * without shift or scaling and without Algorithm 1 parameters: the products
+ * act on the p+1 columns of V only, whatever r is.  Terms are added until two
+ * consecutive ones fall below tol times the block infinity norm, as in
+ * Algorithm 3.  Meant for small |t_k| ||A|| (say up to about 1); for larger
+ * steps it needs many terms and loses accuracy to cancellation (ENOCONV at
+ * the term cap), and phicomb_solve is the method to use.  Arguments, layouts
+ * and ownership as for phicomb_solve; stencil, CSR and dense operators (dense
+ * through its CSR form); EINVAL for a low-rank operator.  stats: s_int = 1,
+ * terms_S = terms summed, the rest 0 apart from status, bytes_alg and ms. */
+int phicomb_solve_series(phicomb_op op, int p, int r, const double *t, const double *beta,
+                         const void *V, double tol, void *W, void *stream,
+                         phicomb_stats_t *stats);
+
 /* ------------------------------------------------------- exponential integrator
  * expRK4s6 (Sec. 1, eq. (expRK4s6): Luan's fourth-order six-stage exponential
  * Runge-Kutta scheme, nodes c2 = c3 = 1/2, c4 = c6 = 1/3, c5 = 5/6) for

@@ -99,6 +99,7 @@ def _lib():
             "phicomb_batch_info": ([P, P, P, P], I32),
             "phicomb_batch_destroy": ([P], I32),
             "phicomb_exprk4s6": ([P, P, P, D, I32, D, I32, P, P, P], I32),
+            "phicomb_solve_series": ([P, I32, I32, P, P, P, D, P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -200,6 +201,21 @@ def phicomb_solve(h, prm: ParamsT, p: int, r: int, t, beta, V, tol: float, preci
                               C.c_void_p(V.data_ptr()), float(tol), int(precision),
                               C.c_void_p(W.data_ptr()), _stream_ptr(stream), C.byref(stats))
     _check(st, "phicomb_solve")
+    return stats
+
+
+def phicomb_solve_series(h, p: int, r: int, t, beta, V, tol: float, W, stream=None) -> StatsT:
+    """The Proposition's single block series (no shift, no scaling)."""
+    ta = np.ascontiguousarray(t, dtype=np.float64)
+    ba = np.ascontiguousarray(beta, dtype=np.float64)
+    _check_device_tensor(V, (None, p + 1), "V")
+    _check_device_tensor(W, (None, r), "W")
+    stats = StatsT()
+    st = _lib().phicomb_solve_series(h, int(p), int(r), _np_ptr(ta), _np_ptr(ba),
+                                     C.c_void_p(V.data_ptr()), float(tol),
+                                     C.c_void_p(W.data_ptr()), _stream_ptr(stream),
+                                     C.byref(stats))
+    _check(st, "phicomb_solve_series")
     return stats
 
 

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libphicomb.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "serve.cpp", "params.hip", "solve.hip", "solve_lowrank.hip", "batch.hip", "exprk.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "params.hip", "solve.hip", "solve_lowrank.hip", "batch.hip", "exprk.hip", "series.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
@@ -40,7 +40,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 7) -> str:
+def build(jobs: int = 8) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
