@@ -74,6 +74,9 @@ def _norm_inf(op) -> float:
         k = 5 if op.dim == 2 else 7
         return float(abs(op.coef[:k]).sum() + abs(op.superdiag))
     import numpy as np
+    if op.kind == "csr":
+        rp, _, va = op.csr()
+        return float(np.add.reduceat(np.abs(va), rp[:-1].astype(np.int64)).max())
     return float(np.abs(op.A).sum(axis=1).max())
 
 
@@ -249,6 +252,44 @@ def bench_exp4(pc, wl, torch) -> dict:
     return out
 
 
+def bench_series(pc, wl, torch) -> dict:
+    """The Proposition's single block series against Algorithm 3 on the
+    convection-diffusion operator (512^2, CSR, p = 3, r = 3, tol 1e-12) at
+    steps scaled so that |t| ||A||_inf is about 0.1, 1 and 10; both timed on
+    the device (kernel events), Algorithm 1 excluded."""
+    import numpy as np
+    pr = wl.config2()
+    op = pc.Operator(pr.op)
+    prm = pc.phicomb_params(op.h, pr.tol, 61, pr.v, 1)
+    nrm = _norm_inf(pr.op)
+    V = torch.from_numpy(pr.V).cuda()
+    W1 = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
+    W2 = torch.empty_like(W1)
+    out = {"workload": "convdiff 512^2 CSR, p=3, r=3, tol 1e-12", "t_norm": [],
+           "series_ms": [], "series_terms": [], "alg3_ms": [], "alg3_s_int": [],
+           "rel_diff": []}
+    for target in (0.1, 1.0, 10.0):
+        t = pr.t / pr.t.max() * (target / nrm)
+        best_s, best_a = None, None
+        for _ in range(3):
+            s1 = pc.phicomb_solve_series(op.h, pr.p, pr.r, t, pr.beta, V, pr.tol, W1)
+            s2 = pc.phicomb_solve(op.h, prm, pr.p, pr.r, t, pr.beta, V, pr.tol, pc.FP64, W2)
+            best_s = s1 if best_s is None or s1.ms < best_s.ms else best_s
+            best_a = s2 if best_a is None or s2.ms < best_a.ms else best_a
+        torch.cuda.synchronize()
+        diff = float((torch.linalg.norm(W1 - W2, dim=0) / torch.linalg.norm(W2, dim=0)).max())
+        print(f"[bench] series |t|A|| = {target:g}: {best_s.ms:.3f} ms ({best_s.terms_S} terms)"
+              f" vs Algorithm 3 {best_a.ms:.3f} ms", file=sys.stderr, flush=True)
+        out["t_norm"].append(target)
+        out["series_ms"].append(best_s.ms)
+        out["series_terms"].append(best_s.terms_S)
+        out["alg3_ms"].append(best_a.ms)
+        out["alg3_s_int"].append(best_a.s_int)
+        out["rel_diff"].append(diff)
+    op.close()
+    return out
+
+
 def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
     """Poisson request stream over a resident operator pool (70 % 2-D/3-D
     stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
@@ -333,6 +374,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision and served-stream measurements")
+    ap.add_argument("--extras", default=None,
+                    help="comma-separated subset of the extra sections to run (mixed_tol1e-6, "
+                         "batched, exp2, exp3, exp4, series, served); default all")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -433,27 +477,26 @@ def main(argv=None) -> int:
               flush=True)
 
     progress("headline workload", t0)
+    sections = [
+        ("mixed_tol1e-6", "mixed precision", lambda: bench_mixed(pc, wl, torch, reps=5)),
+        ("batched", "batched", lambda: bench_batched(pc, wl, torch, reps=1)),
+        ("exp2", "second experiment", lambda: bench_exp2(pc, wl, torch)),
+        ("exp3", "third experiment", lambda: bench_exp3(pc, wl, torch)),
+        ("exp4", "fourth experiment", lambda: bench_exp4(pc, wl, torch)),
+        ("series", "single block series", lambda: bench_series(pc, wl, torch)),
+    ]
+    if args.serve_seconds > 0:
+        sections.append(("served", "served stream",
+                         lambda: bench_served(pc, wl, torch, args.serve_seconds,
+                                              args.serve_rate, args.serve_slots)))
+    wanted = None if args.extras is None else set(args.extras.split(","))
     if not args.no_extras:
-        t1 = time.perf_counter()
-        line["mixed_tol1e-6"] = bench_mixed(pc, wl, torch, reps=5)
-        progress("mixed precision", t1)
-        t1 = time.perf_counter()
-        line["batched"] = bench_batched(pc, wl, torch, reps=1)
-        progress("batched", t1)
-        t1 = time.perf_counter()
-        line["exp2"] = bench_exp2(pc, wl, torch)
-        progress("second experiment", t1)
-        t1 = time.perf_counter()
-        line["exp3"] = bench_exp3(pc, wl, torch)
-        progress("third experiment", t1)
-        t1 = time.perf_counter()
-        line["exp4"] = bench_exp4(pc, wl, torch)
-        progress("fourth experiment", t1)
-        if args.serve_seconds > 0:
+        for key, what, fn in sections:
+            if wanted is not None and key not in wanted:
+                continue
             t1 = time.perf_counter()
-            line["served"] = bench_served(pc, wl, torch, args.serve_seconds, args.serve_rate,
-                                          args.serve_slots)
-            progress("served stream", t1)
+            line[key] = fn()
+            progress(what, t1)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pr)
     else:
