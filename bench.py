@@ -35,7 +35,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("internal.h", "solve.hip"):
+    for f in ("internal.h", "solve_body.h", "solve.hip"):
         with open(os.path.join(ROOT, "paper_2509_26475_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
