@@ -116,3 +116,30 @@ def test_exprk4s6_rejects_bad_arguments():
         pc.phicomb_exprk4s6(lr.h, prm, gc, 1e-3, 1, TOL, pc.FP64, u)
     assert e.value.status == pc.EINVAL
     lr.close()
+
+
+@pytest.mark.parametrize("kind", ["stencil", "dense"])
+def test_exprk4s6_other_operator_kinds(kind):
+    """The right-hand side through the stencil row product (a 2-D Laplacian
+    stencil) and through a dense operator's CSR form, against the oracle's
+    integrator with pinned parameters."""
+    if kind == "stencil":
+        op = wl.laplacian_2d(40, kappa=1e-3)
+        u0 = wl.adr_initial(40)
+    else:
+        rng = np.random.default_rng(5)
+        A = rng.standard_normal((300, 300)) * 0.2 - np.diag(rng.uniform(0, 30, 300))
+        op = wl.Dense(np.ascontiguousarray(A))
+        u0 = rng.uniform(0, 1, 300)
+    gc = wl.adr_reaction(50.0)
+    h = 1e-3
+    po = oracle.params(op, TOL, wl.params_vector(op.n))
+    say(f"[gpu] expRK4s6 {kind} n={op.n} 20 steps pinned")
+    uo, calls = oracle.exprk4s6(op, gc, u0, h, 20, TOL, po["shift"], po["s"])
+    H = pc.Operator(op)
+    ug, st = _run_gpu(H, pc.params_from_dict(po), gc, u0, h, 20)
+    H.close()
+    err = np.abs(ug - uo).max() / np.abs(uo).max()
+    say(f"      err {err:.2e} terms {st['terms']}")
+    assert st["status"] == pc.OK and st["calls"] == 80
+    assert err <= 1e-10, err
