@@ -273,8 +273,11 @@ int phicomb_solve_series(phicomb_op op, int p, int r, const double *t, const dou
  * Algorithm 1 (computed once for A and tol and reused, Sec. 6); tol and
  * precision as for phicomb_solve.  The operator must be a stencil, CSR or
  * dense operator (EINVAL for low rank).  Stage buffers (8 n doubles) stay
- * with the operator.  Blocking; the first failing call's status is returned
- * and u then holds the last completed step.  stats may be NULL. */
+ * with the operator.  The workgroup slots of the solves are held for the
+ * whole integration and the host does not wait for individual calls.
+ * Blocking; the first failing call's status is returned and u then holds
+ * the last completed step (a failure is noticed within 64 steps; the steps
+ * after it leave u unchanged).  stats may be NULL. */
 typedef struct {
     int32_t steps;          /* steps completed */
     int32_t calls;          /* Algorithm 3 calls (4 per step) */
@@ -283,7 +286,6 @@ typedef struct {
     int64_t terms;          /* Taylor terms over all calls (S-series + recovery) */
     int64_t fp32_terms;     /* mixed precision: recovery terms evaluated in FP32 */
     double ms;              /* device time of the whole integration, milliseconds */
-    double kernel_ms;       /* device time of the solve kernels alone */
 } phicomb_exprk_stats_t;
 
 int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, const double g[4], double h,

@@ -56,7 +56,7 @@ class StatsT(C.Structure):
 class ExprkStatsT(C.Structure):
     _fields_ = [("steps", C.c_int32), ("calls", C.c_int32), ("max_s_int", C.c_int32),
                 ("status", C.c_int32), ("terms", C.c_int64), ("fp32_terms", C.c_int64),
-                ("ms", C.c_double), ("kernel_ms", C.c_double)]
+                ("ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

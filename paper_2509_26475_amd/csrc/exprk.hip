@@ -13,10 +13,18 @@
 // scheme's phi_1, phi_2, phi_3 coefficients.  Between the calls, one pointwise
 // kernel per stage forms U_i = u_n + w_i, the increments D_i and the next
 // input block, so nothing leaves the device.
+//
+// The host does not wait for each call: the workgroup slots for the solves
+// are taken from the ledger once for the whole integration, every solve is
+// launched without a host synchronisation, and a one-thread kernel after it
+// folds the call's status and term counts into a device accumulator.  The
+// update u <- u + w of a step is skipped once any call has failed, so u keeps
+// the last completed step; the host reads the accumulator every kCheckEvery
+// steps and at the end, and stops at the first failure it sees.
 #include <cmath>
 #include <cstring>
 
-#include "internal.h"
+#include "solve_body.h"
 
 namespace phc {
 
@@ -88,12 +96,37 @@ __global__ __launch_bounds__(kENT) void exprk_stage_pair(int64_t n, Cubic g, dou
     V[row * 4 + 3] = h * (la * da + lb * db);
 }
 
+// u <- u + w, unless a call of the integration has failed.
 __global__ __launch_bounds__(kENT) void exprk_update(int64_t n, double *__restrict__ u,
-                                                     const double *__restrict__ W) {
+                                                     const double *__restrict__ W,
+                                                     const long long *__restrict__ acc) {
     const int64_t row = (int64_t)blockIdx.x * kENT + threadIdx.x;
-    if (row < n)
+    if (row < n && acc[0] == 0)
         u[row] = u[row] + W[row];
 }
+
+// acc: first non-zero status, Taylor terms, FP32 terms, calls, steps completed.
+__global__ void exprk_acc_init(long long *acc) {
+    if (threadIdx.x < 8)
+        acc[threadIdx.x] = 0;
+}
+
+__global__ void exprk_fold(const int *__restrict__ info, long long *acc) {
+    if (threadIdx.x == 0) {
+        if (acc[0] == 0 && info[0] != 0)
+            acc[0] = info[0];
+        acc[1] += (long long)info[1] + info[2];
+        acc[2] += info[4];
+        acc[3] += 1;
+    }
+}
+
+__global__ void exprk_step_done(long long *acc) {
+    if (threadIdx.x == 0 && acc[0] == 0)
+        acc[4] += 1;
+}
+
+constexpr int kCheckEvery = 64;   // steps between host reads of the accumulator
 
 }  // namespace phc
 
@@ -134,8 +167,8 @@ extern "C" int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, cons
     int st = ensure_workspace(op, need);
     if (st != PHICOMB_OK)
         return st;
-    // gu, hf: n each; V: n x 4; W: n x 2
-    const size_t aux_bytes = sizeof(double) * (size_t)n * 8;
+    // gu, hf: n each; V: n x 4; W: n x 2; the accumulator
+    const size_t aux_bytes = sizeof(double) * ((size_t)n * 8 + 8);
     if (op->aux.bytes < aux_bytes) {
         if (op->aux.ptr)
             hipFree(op->aux.ptr);
@@ -149,22 +182,49 @@ extern "C" int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, cons
     double *hf = gu + n;
     double *V = hf + n;
     double *W = V + 4 * n;
+    long long *accd = (long long *)(W + 2 * n);
     double *ud = (double *)u;
     const unsigned grid = (unsigned)((n + kENT - 1) / kENT);
+
+    // workgroup slots for every solve of the integration, held until the end
+    const int want = (int)std::min<int64_t>(device_cus(op->device), (n + kNT - 1) / kNT);
+    const int slots = cu_acquire(op->device, want, want);
+    if (slots < 1)
+        return PHICOMB_EDEVICE;
+    struct Hold {
+        int dev, g;
+        hipStream_t s;
+        ~Hold() {
+            hipStreamSynchronize(s);   // every solve has completed before the slots return
+            cu_release(dev, g);
+        }
+    } hold{op->device, slots, stream};
 
     phicomb_exprk_stats_t acc;
     std::memset(&acc, 0, sizeof(acc));
     auto call = [&](int p, int r, const double *t, const double *beta) -> int {
-        phicomb_stats_t s;
-        std::memset(&s, 0, sizeof(s));
-        const int rc = solve_run(op, prm, p, r, t, beta, V, tol, precision, W, stream, &s,
-                                 op->ws.ptr, op->ws.bytes, op->pinned);
-        acc.calls += 1;
-        acc.terms += (long long)s.terms_S + s.terms_rec;
-        acc.fp32_terms += s.fp32_terms;
-        acc.max_s_int = std::max(acc.max_s_int, s.s_int);
-        acc.kernel_ms += s.ms;
-        return rc;
+        const int *info = nullptr;
+        int s_int = 0;
+        const int rc = solve_launch_held(op, prm, p, r, t, beta, V, tol, precision, W, stream,
+                                         op->ws.ptr, op->ws.bytes, slots, &info, &s_int);
+        if (rc != PHICOMB_OK)
+            return rc;
+        exprk_fold<<<1, 64, 0, stream>>>(info, accd);
+        acc.max_s_int = std::max(acc.max_s_int, s_int);
+        return PHICOMB_OK;
+    };
+    // device accumulator -> acc; its status
+    auto check = [&]() -> int {
+        if (hipMemcpyAsync(op->pinned, accd, 8 * sizeof(long long), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return PHICOMB_EDEVICE;
+        const long long *h = (const long long *)op->pinned;
+        acc.terms = h[1];
+        acc.fp32_terms = h[2];
+        acc.calls = (int)h[3];
+        acc.steps = (int)h[4];
+        return (int)h[0];
     };
     const double t2[1] = {c2 * h};
     const double b2[2] = {0.0, c2};
@@ -178,6 +238,7 @@ extern "C" int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, cons
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    exprk_acc_init<<<1, 64, 0, stream>>>(accd);
     if (timed)
         hipEventRecord(e0, stream);
     st = PHICOMB_OK;
@@ -199,19 +260,24 @@ extern "C" int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, cons
                                                     -1.0 / c6, ud, gu, hf, W, V);
         if ((st = call(3, 1, t1, b1)) != PHICOMB_OK)
             break;
-        exprk_update<<<grid, kENT, 0, stream>>>(n, ud, W);
-        acc.steps += 1;
+        exprk_update<<<grid, kENT, 0, stream>>>(n, ud, W, accd);
+        exprk_step_done<<<1, 64, 0, stream>>>(accd);
+        if ((step + 1) % kCheckEvery == 0)
+            st = check();
     }
-    if (timed) {
+    if (timed)
         hipEventRecord(e1, stream);
+    // the accumulator holds the first failing call's status, if any
+    const int dev_st = check();
+    if (st == PHICOMB_OK)
+        st = dev_st;
+    if (timed) {
         float ms = 0.0f;
-        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
             acc.ms = ms;
         hipEventDestroy(e0);
         hipEventDestroy(e1);
     }
-    if (st == PHICOMB_OK && hipStreamSynchronize(stream) != hipSuccess)
-        st = PHICOMB_EDEVICE;
     acc.status = st;
     if (stats)
         *stats = acc;

@@ -237,6 +237,28 @@ int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, c
     return PHICOMB_OK;
 }
 
+int solve_launch_held(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+                      const double *beta, const void *V, double tol, int precision, void *W,
+                      hipStream_t stream, void *ws, size_t ws_bytes, int slots,
+                      const int **info_dev, int *s_int) {
+    SolveArgs a;
+    const int st = build_solve_args(op, prm, p, r, t, beta, V, tol, precision, W, ws, ws_bytes, a);
+    if (st != PHICOMB_OK)
+        return st;
+    const int64_t wgs_needed1 = (op->dev.n + kNT - 1) / kNT;
+    int64_t G = 0;
+    KernelFn fn = select_variant(op, r, precision == PHICOMB_MIXED, wgs_needed1, slots, &G);
+    if (!fn)
+        return PHICOMB_EINVAL;
+    solve_sync_init<<<1, 256, 0, stream>>>(a.bar, a.info);
+    void *args[] = {&a};
+    if (launch_persistent((const void *)fn, (unsigned)G, kNT, args, stream) != hipSuccess)
+        return PHICOMB_EDEVICE;
+    *info_dev = a.info;
+    *s_int = a.s_int;
+    return PHICOMB_OK;
+}
+
 double solve_algorithmic_bytes(phicomb_op op, int p, int r, int s_int, const int *info) {
     return algorithmic_bytes(op->dev, op->nnz, op->dev.n, p, r, info[1], info[2], s_int, info[4]);
 }

@@ -729,6 +729,15 @@ size_t solve_sync_bytes();
 int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
                      const double *beta, const void *V, double tol, int precision, void *W,
                      void *ws, size_t ws_bytes, SolveArgs &a);
+// Launches one solve on stream within `slots` workgroup slots that the
+// caller already holds from the ledger (kept until the kernel has completed)
+// and returns without waiting: *info_dev points at the kernel's status and
+// term counts (status, terms_S, terms_rec, max_terms_step, fp32_terms), valid
+// once the kernel has run and until the next launch on this workspace.
+int solve_launch_held(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+                      const double *beta, const void *V, double tol, int precision, void *W,
+                      hipStream_t stream, void *ws, size_t ws_bytes, int slots,
+                      const int **info_dev, int *s_int);
 // Algorithmic bytes of a finished solve (info as written by the kernel).
 double solve_algorithmic_bytes(phicomb_op op, int p, int r, int s_int, const int *info);
 

@@ -177,3 +177,17 @@ def test_lowrank_rejects_bad_shapes():
                                   V[:, :2].contiguous(), W, 1e-8)], pc.FP64)
     assert e.value.status == pc.EINVAL
     h.close()
+
+
+def test_lowrank_maximum_rank():
+    """rank 16 (the largest accepted) with r = 2 abscissae: 96 entries of W^T X
+    per exchange; a diagonal core with eigenvalues -1 .. -16."""
+    core = np.diag(-np.arange(1.0, 17.0))
+    op = wl.lowrank_operator(core, 5000)
+    rng = np.random.default_rng(9)
+    p, r = 1, 2
+    pr = wl.Problem("lowrank_rank16", op, p, r, np.array([0.3, 1.0]),
+                    rng.uniform(-1, 1, (r, p + 1)),
+                    np.ascontiguousarray(rng.standard_normal((op.n, p + 1))), 2.0 ** -53,
+                    wl.params_vector(op.n))
+    _pinned(pr, "rank 16")

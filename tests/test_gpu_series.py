@@ -81,3 +81,22 @@ def test_series_rejects_low_rank_and_bad_args():
         pc.phicomb_solve_series(op.h, 1, 1, [np.inf], [[1.0, 1.0]], V, 1e-8, W)
     assert e.value.status == pc.EINVAL
     op.close()
+
+
+def test_series_largest_block():
+    """p = 7, r = 4 (the largest block) on a 2-D Laplacian stencil, general
+    weights, |t| ||A|| about 2."""
+    op = wl.laplacian_2d(60)
+    rng = np.random.default_rng(12)
+    p, r = 7, 4
+    nrm = float(np.abs(op.coef[:5]).sum())
+    pr = wl.Problem("series_p7_r4", op, p, r, rng.uniform(0.2, 1.0, r) * 2.0 / nrm,
+                    rng.uniform(-1, 1, (r, p + 1)),
+                    np.ascontiguousarray(rng.standard_normal((op.n, p + 1))), 1e-13,
+                    wl.params_vector(op.n))
+    Wo, so = oracle.series_block(pr.op, p, r, pr.t, pr.beta, pr.V, pr.tol)
+    Wg, sg = _gpu_series(pr)
+    err = refs.rel2_cols(Wg, Wo).max()
+    say(f"[gpu] series p=7 r=4: terms {sg['terms_S']}/{so['terms']} err {err:.2e}")
+    assert abs(sg["terms_S"] - so["terms"]) <= 1
+    assert err <= 1e-12
