@@ -58,14 +58,45 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(problem) -> dict:
+def cpu_baseline(problem, extras: bool = True) -> dict:
     import oracle
     t0 = time.perf_counter()
     W, st, prm = oracle.full(problem)
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "one full step (Algorithm 1 + Algorithm 3) of the same workload, "
-                      f"single-threaded C, {dt:.2f} s"}
+    out = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "one full step (Algorithm 1 + Algorithm 3) of the same workload, "
+                     f"single-threaded C, {dt:.2f} s"}
+    if extras:
+        out["others"] = cpu_baseline_others(oracle)
+    return out
+
+
+def cpu_baseline_others(oracle) -> dict:
+    """The oracle (single thread) on bounded samples of the other measured
+    workloads, in the units of their bench sections."""
+    import workloads as wl
+    res = {}
+    # third experiment: one (core, t), parameters + solve
+    pr = wl.exp3_problem("M2", 10.0, seed=0)
+    t0 = time.perf_counter()
+    oracle.full(pr)
+    res["exp3_M2_t10_total_ms"] = 1e3 * (time.perf_counter() - t0)
+    # fourth experiment: the first 64 steps at h_1 (the integration has 512)
+    op = wl.adr_operator(wl.ADR["N"])
+    gc = wl.adr_reaction(wl.ADR["gamma"])
+    u0 = wl.adr_initial(wl.ADR["N"])
+    po = oracle.params(op, 1e-7, wl.params_vector(op.n))
+    h, _ = wl.adr_steps(1)
+    t0 = time.perf_counter()
+    oracle.exprk4s6(op, gc, u0, h, 64, 1e-7, po["shift"], po["s"])
+    res["exp4_h1_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / 64
+    # single block series: convection-diffusion 512^2 at |t| ||A|| = 1
+    pr = wl.config2()
+    t = pr.t / pr.t.max() * (1.0 / _norm_inf(pr.op))
+    t0 = time.perf_counter()
+    oracle.series_block(pr.op, pr.p, pr.r, t, pr.beta, pr.V, pr.tol)
+    res["series_tnorm1_ms"] = 1e3 * (time.perf_counter() - t0)
+    return res
 
 
 def _norm_inf(op) -> float:
@@ -498,7 +529,7 @@ def main(argv=None) -> int:
             line[key] = fn()
             progress(what, t1)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(pr)
+        line["cpu_baseline"] = cpu_baseline(pr, extras=not args.no_extras)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
