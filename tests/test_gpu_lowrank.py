@@ -191,3 +191,42 @@ def test_lowrank_maximum_rank():
                     np.ascontiguousarray(rng.standard_normal((op.n, p + 1))), 2.0 ** -53,
                     wl.params_vector(op.n))
     _pinned(pr, "rank 16")
+
+
+def test_lowrank_served_matches_blocking_solve():
+    """Low-rank requests through phicomb_submit / phicomb_poll (the worker's
+    workspace includes the W^T X exchange area) give the blocking solve's
+    result bit for bit; three cores in flight together."""
+    import time
+    import torch
+    pc.phicomb_serve_config(0, 4)
+    probs = [wl.exp3_problem(c, t, n=30000, seed=5) for c, t in
+             (("M1", 10.0), ("M2", 1.0), ("M3", 1e-3))]
+    ops = [pc.Operator(pr.op) for pr in probs]
+    prms = [pc.params_from_dict(oracle.params(pr.op, pr.tol, pr.v)) for pr in probs]
+    Vd = [torch.from_numpy(pr.V).cuda() for pr in probs]
+    Wb = [torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda") for pr in probs]
+    Ws = [torch.full((pr.n, pr.r), np.nan, dtype=torch.float64, device="cuda") for pr in probs]
+    for k, pr in enumerate(probs):
+        pc.phicomb_solve(ops[k].h, prms[k], pr.p, pr.r, pr.t, pr.beta, Vd[k], pr.tol, pc.FP64,
+                         Wb[k])
+    torch.cuda.synchronize()
+    tickets = [pc.phicomb_submit(ops[k].h, prms[k], pr.p, pr.r, pr.t, pr.beta, Vd[k], pr.tol,
+                                 pc.FP64, Ws[k]) for k, pr in enumerate(probs)]
+    done = [None] * len(tickets)
+    t_end = time.perf_counter() + 60.0
+    while any(d is None for d in done):
+        assert time.perf_counter() < t_end, "served requests did not complete"
+        for i, tk in enumerate(tickets):
+            if done[i] is None:
+                st, _ = pc.phicomb_poll(tk)
+                if st != pc.PENDING:
+                    done[i] = st
+        time.sleep(0.0005)
+    torch.cuda.synchronize()
+    say(f"[gpu] lowrank served: statuses {done}")
+    assert all(d == pc.OK for d in done)
+    for k in range(len(probs)):
+        assert torch.equal(Ws[k], Wb[k]), k
+    for o in ops:
+        o.close()
