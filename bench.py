@@ -321,6 +321,31 @@ def bench_series(pc, wl, torch) -> dict:
     return out
 
 
+def bench_spmm(pc, wl, torch) -> dict:
+    """The block product Y = (A - xi I) X alone on the 128^3 Laplacian
+    (n = 2^21) as a 7-point stencil and as CSR, c = 4, 6, 12 columns:
+    algorithmic bytes (X read and Y written once, 16 n c, plus the CSR arrays
+    12 nnz + 4 (n + 1)) over the device time, best of 10."""
+    pr = wl.config3()
+    st = pr.op
+    rp, ci, va = st.csr()
+    out = {"workload": "128^3 Laplacian, n=2^21, Y = (A - xi I) X", "rows": []}
+    for kind, desc in (("stencil", st), ("csr", wl.CSR(st.n, rp, ci, va))):
+        op = pc.Operator(desc)
+        opb = 0.0 if kind == "stencil" else 12.0 * len(va) + 4.0 * (st.n + 1)
+        for c in (4, 6, 12):
+            X = torch.randn((c, st.n), dtype=torch.float64, device="cuda")
+            Y = torch.empty_like(X)
+            best = min(pc.phicomb_op_apply(op.h, X, 0.5, Y, timed=True) for _ in range(10))
+            gbs = (16.0 * st.n * c + opb) / (best * 1e-3) / 1e9
+            print(f"[bench] block product {kind} c={c}: {best * 1e3:.1f} us {gbs:.0f} GB/s",
+                  file=sys.stderr, flush=True)
+            out["rows"].append({"kind": kind, "cols": c, "us": best * 1e3, "GBps": gbs,
+                                "hbm_frac": gbs / HBM_PEAK_GBS})
+        op.close()
+    return out
+
+
 def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
     """Poisson request stream over a resident operator pool (70 % 2-D/3-D
     stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
@@ -407,7 +432,7 @@ def main(argv=None) -> int:
                     help="skip the mixed-precision and served-stream measurements")
     ap.add_argument("--extras", default=None,
                     help="comma-separated subset of the extra sections to run (mixed_tol1e-6, "
-                         "batched, exp2, exp3, exp4, series, served); default all")
+                         "batched, exp2, exp3, exp4, series, spmm, served); default all")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -515,6 +540,7 @@ def main(argv=None) -> int:
         ("exp3", "third experiment", lambda: bench_exp3(pc, wl, torch)),
         ("exp4", "fourth experiment", lambda: bench_exp4(pc, wl, torch)),
         ("series", "single block series", lambda: bench_series(pc, wl, torch)),
+        ("spmm", "block product", lambda: bench_spmm(pc, wl, torch)),
     ]
     if args.serve_seconds > 0:
         sections.append(("served", "served stream",

@@ -245,6 +245,16 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
 
 int phicomb_batch_destroy(phicomb_batch b);
 
+/* Block product Y = (A - shift I) X, the operation every Taylor term of
+ * Algorithms 1-3 is built from (A is accessed only through products).  X and
+ * Y: device arrays, column-major n x ncols (column c at offset c n), caller
+ * owned, not overlapping; 1 <= ncols <= 64.  Stencil, CSR and dense operators
+ * (dense through its CSR form); EINVAL for a low-rank operator.  Enqueued on
+ * stream; when ms is not NULL the call waits for the product and stores its
+ * device time in milliseconds. */
+int phicomb_op_apply(phicomb_op op, const void *X, int ncols, double shift, void *Y,
+                     void *stream, double *ms);
+
 /* The single block series of the Proposition in Sec. 4 with g_i = phi_i:
  * W[:, k] = sum_i beta[k][i] phi_i(t_k A) v_i evaluated as
  * sum_j A^j V D_j Gamma T^j (D_j = diag(1/(i+j)!), Gamma[i][k] = beta[k][i]),

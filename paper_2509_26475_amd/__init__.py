@@ -100,6 +100,7 @@ def _lib():
             "phicomb_batch_destroy": ([P], I32),
             "phicomb_exprk4s6": ([P, P, P, D, I32, D, I32, P, P, P], I32),
             "phicomb_solve_series": ([P, I32, I32, P, P, P, D, P, P, P], I32),
+            "phicomb_op_apply": ([P, P, I32, D, P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -202,6 +203,24 @@ def phicomb_solve(h, prm: ParamsT, p: int, r: int, t, beta, V, tol: float, preci
                               C.c_void_p(W.data_ptr()), _stream_ptr(stream), C.byref(stats))
     _check(st, "phicomb_solve")
     return stats
+
+
+def phicomb_op_apply(h, X, shift: float, Y, stream=None, timed: bool = False) -> float:
+    """Y = (A - shift I) X; X, Y: torch float64 cuda tensors [ncols][n]
+    (column-major blocks).  Returns the device time in ms when timed."""
+    import torch
+    for name, x in (("X", X), ("Y", Y)):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 \
+                or not x.is_contiguous() or x.dim() != 2:
+            raise TypeError(f"{name} must be a contiguous float64 cuda tensor [ncols][n]")
+    if X.shape != Y.shape:
+        raise ValueError("X and Y must have the same shape")
+    ms = C.c_double(0.0)
+    st = _lib().phicomb_op_apply(h, C.c_void_p(X.data_ptr()), int(X.shape[0]), float(shift),
+                                 C.c_void_p(Y.data_ptr()), _stream_ptr(stream),
+                                 C.byref(ms) if timed else None)
+    _check(st, "phicomb_op_apply")
+    return ms.value
 
 
 def phicomb_solve_series(h, p: int, r: int, t, beta, V, tol: float, W, stream=None) -> StatsT:

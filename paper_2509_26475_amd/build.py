@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libphicomb.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "serve.cpp", "params.hip", "solve.hip", "solve_lowrank.hip", "batch.hip", "exprk.hip", "series.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "params.hip", "solve.hip", "solve_lowrank.hip", "batch.hip", "exprk.hip", "series.hip", "apply.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",

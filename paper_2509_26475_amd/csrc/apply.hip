@@ -1,0 +1,102 @@
+// Block product Y = (A - shift I) X on its own: the operation every Taylor
+// term of Algorithms 1-3 is built from (the paper accesses A only through
+// such products).  Used to measure what the product alone reaches on HBM.
+//
+// One thread per row, 256-row workgroups mapped so that each XCD gets a
+// contiguous range of rows (neighbouring rows of a stencil or banded CSR
+// operator then share an L2); the columns are processed in compile-time
+// chunks of NC so that a CSR row's indices and values are read once per
+// chunk.  X and Y are column-major (column c at X + c n).
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace phc {
+
+constexpr int kANT = 256;
+
+template <int KIND, int NC>
+__global__ __launch_bounds__(kANT) void apply_kernel(DevOp A, const double *__restrict__ X,
+                                                     int ncols, double shift,
+                                                     double *__restrict__ Y) {
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t row = (int64_t)b * kANT + threadIdx.x;
+    const int64_t n = A.n;
+    if (row >= n)
+        return;
+    const RowCtx rc = row_ctx<KIND>(A, row);
+    for (int c0 = 0; c0 < ncols; c0 += NC) {
+        double y[NC];
+        apply_cols<KIND, NC>(A, rc, X, n, c0, shift, y);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+            Y[(int64_t)(c0 + j) * n + row] = y[j];
+    }
+}
+
+using ApplyFn = void (*)(DevOp, const double *, int, double, double *);
+
+template <int KIND>
+static ApplyFn apply_fn(int ncols) {
+    // the widest chunk that divides the column count
+    if (ncols % 12 == 0)
+        return apply_kernel<KIND, 12>;
+    if (ncols % 8 == 0)
+        return apply_kernel<KIND, 8>;
+    if (ncols % 6 == 0)
+        return apply_kernel<KIND, 6>;
+    if (ncols % 4 == 0)
+        return apply_kernel<KIND, 4>;
+    if (ncols % 3 == 0)
+        return apply_kernel<KIND, 3>;
+    if (ncols % 2 == 0)
+        return apply_kernel<KIND, 2>;
+    return apply_kernel<KIND, 1>;
+}
+
+}  // namespace phc
+
+using namespace phc;
+
+extern "C" int phicomb_op_apply(phicomb_op op, const void *X, int ncols, double shift, void *Y,
+                                void *stream_, double *ms) {
+    if (ms)
+        *ms = 0.0;
+    if (!op || !X || !Y || ncols < 1 || ncols > 64 || !std::isfinite(shift))
+        return PHICOMB_EINVAL;
+    const int kind = op->dev.kind;
+    if (kind == kLowRank)
+        return PHICOMB_EINVAL;
+    // dense operators through their CSR form
+    ApplyFn fn = (kind == kStencil) ? apply_fn<kStencil>(ncols) : apply_fn<kCsr>(ncols);
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t n = op->dev.n;
+    const int64_t blocks = (n + kANT - 1) / kANT;
+    if (blocks > 0x7fffffff)
+        return PHICOMB_EINVAL;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = ms && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (timed)
+        hipEventRecord(e0, stream);
+    fn<<<(unsigned)blocks, kANT, 0, stream>>>(op->dev, (const double *)X, ncols, shift,
+                                              (double *)Y);
+    if (hipGetLastError() != hipSuccess) {
+        if (timed) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+        }
+        return PHICOMB_EDEVICE;
+    }
+    int st = PHICOMB_OK;
+    if (timed) {
+        hipEventRecord(e1, stream);
+        float t = 0.0f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            st = PHICOMB_EDEVICE;
+        *ms = t;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+    }
+    return st;
+}
