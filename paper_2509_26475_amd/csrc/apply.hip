@@ -4,11 +4,13 @@
 //
 // One thread per row, 256-row workgroups mapped so that each XCD gets a
 // contiguous range of rows (neighbouring rows of a stencil or banded CSR
-// operator then share an L2); the columns are processed in compile-time
-// chunks of NC so that a CSR row's indices and values are read once per
-// chunk.  X and Y are column-major (column c at X + c n).
+// operator then share an L2).  Up to 16 columns are done by a kernel of that
+// exact width; wider blocks in compile-time chunks of NC, so that a CSR row's
+// indices and values are read once per chunk.  X and Y are column-major
+// (column c at X + c n).
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "internal.h"
 
@@ -35,11 +37,39 @@ __global__ __launch_bounds__(kANT) void apply_kernel(DevOp A, const double *__re
     }
 }
 
+// Exactly NC columns: no column loop (a runtime chunk loop costs about a
+// third of the bandwidth on the 128^3 stencil).
+template <int KIND, int NC>
+__global__ __launch_bounds__(kANT) void apply_kernel_exact(DevOp A, const double *__restrict__ X,
+                                                           int, double shift,
+                                                           double *__restrict__ Y) {
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t row = (int64_t)b * kANT + threadIdx.x;
+    const int64_t n = A.n;
+    if (row >= n)
+        return;
+    const RowCtx rc = row_ctx<KIND>(A, row);
+    double y[NC];
+    apply_cols<KIND, NC>(A, rc, X, n, 0, shift, y);
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        Y[(int64_t)j * n + row] = y[j];
+}
+
 using ApplyFn = void (*)(DevOp, const double *, int, double, double *);
+
+template <int KIND, int... Q>
+static ApplyFn exact_fn(int ncols, std::integer_sequence<int, Q...>) {
+    ApplyFn fn = nullptr;
+    ((ncols == Q + 1 ? (fn = apply_kernel_exact<KIND, Q + 1>, 0) : 0), ...);
+    return fn;
+}
 
 template <int KIND>
 static ApplyFn apply_fn(int ncols) {
-    // the widest chunk that divides the column count
+    if (ncols <= 16)
+        return exact_fn<KIND>(ncols, std::make_integer_sequence<int, 16>{});
+    // wider blocks: the widest chunk that divides the column count
     if (ncols % 12 == 0)
         return apply_kernel<KIND, 12>;
     if (ncols % 8 == 0)
