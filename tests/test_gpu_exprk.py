@@ -143,3 +143,26 @@ def test_exprk4s6_other_operator_kinds(kind):
     say(f"      err {err:.2e} terms {st['terms']}")
     assert st["status"] == pc.OK and st["calls"] == 80
     assert err <= 1e-10, err
+
+
+def test_exprk4s6_failing_call_leaves_last_completed_step(monkeypatch):
+    """A term cap of 2 (forced from the host) makes the first call of the
+    first step stop with ENOCONV; the status comes back and u keeps its
+    initial value (every step's update is skipped once a call has failed)."""
+    import torch
+    op, gc, u0 = _setup()
+    h, _ = wl.adr_steps(1)
+    H = pc.Operator(op)
+    prm = H.params(TOL, v=wl.params_vector(op.n))
+    u = torch.from_numpy(u0.copy()).cuda()
+    monkeypatch.setenv("PHICOMB_TERM_CAP", "2")
+    with pytest.raises(pc.PhicombError) as e:
+        pc.phicomb_exprk4s6(H.h, prm, gc, h, 3, TOL, pc.FP64, u)
+    monkeypatch.delenv("PHICOMB_TERM_CAP")
+    torch.cuda.synchronize()
+    assert e.value.status == pc.ENOCONV
+    assert np.array_equal(u.cpu().numpy(), u0)
+    # and the operator still integrates normally afterwards
+    ug, st = _run_gpu(H, prm, gc, u0, h, 4)
+    assert st["status"] == pc.OK and st["steps"] == 4
+    H.close()
