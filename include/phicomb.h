@@ -264,8 +264,9 @@ int phicomb_op_apply(phicomb_op op, const void *X, int ncols, double shift, void
  * Algorithm 3.  Meant for small |t_k| ||A|| (say up to about 1); for larger
  * steps it needs many terms and loses accuracy to cancellation (ENOCONV at
  * the term cap), and phicomb_solve is the method to use.  Arguments, layouts
- * and ownership as for phicomb_solve; stencil, CSR and dense operators (dense
- * through its CSR form); EINVAL for a low-rank operator.  stats: s_int = 1,
+ * and ownership as for phicomb_solve; every operator kind (dense through its
+ * CSR form; low rank with W^T P_j summed in each term's exchange, which needs
+ * rank (p+1) <= 256).  stats: s_int = 1,
  * terms_S = terms summed, the rest 0 apart from status, bytes_alg and ms. */
 int phicomb_solve_series(phicomb_op op, int p, int r, const double *t, const double *beta,
                          const void *V, double tol, void *W, void *stream,

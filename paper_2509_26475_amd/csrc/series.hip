@@ -33,6 +33,7 @@ struct SeriesArgs {
     double *X0, *X1;                    // [p+1][n] ping-pong
     unsigned *bar;
     double *part;                       // [2][kMaxGrid][2]
+    double *lrpart;                     // low rank: [2][rank (p+1)][kMaxGrid] partial W^T P_j
     int *info;                          // status, terms
 };
 
@@ -48,6 +49,7 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
     __shared__ double red[kNT / 64][2];
     __shared__ double wk[kRMax][kPMax1];   // this term's weight of P_j[:, i] in column k
     __shared__ double rpow[kRMax];         // (t_k / tau)^j
+    __shared__ double lrc[kLrVals];        // low rank: W^T P_j of the coming product
     __shared__ int ok;
     const unsigned G = gridDim.x, bid = blockIdx.x;
     const int lb = xcd_logical_block(bid, G);
@@ -70,10 +72,19 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
         return;
     }
     unsigned epoch = 0;
-    auto exchange = [&](double (&v)[2]) -> bool {
+    // low rank (A = U W^T): the pass that writes P_j also leaves this
+    // workgroup's partial W^T P_j, summed by every workgroup after the exchange
+    const int nlr = (KIND == kLowRank) ? A.rank * P1 : 0;
+    auto lr_part = [&]() { return P.lrpart + (size_t)(epoch & 1) * nlr * kMaxGrid; };
+    auto exchange = [&](double (&v)[2], const double *Xw) -> bool {
+        if constexpr (KIND == kLowRank)
+            lr_publish(A, n, lo, hi, Xw, P1, 0, lr_part(), single ? 0u : bid);
         if (single) {
             wait_own_stores();
             workgroup_max<2, kNT>(v, red);
+            if constexpr (KIND == kLowRank)
+                lr_gather(lr_part(), 1, nlr, lrc);
+            ++epoch;
             return true;
         }
         double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
@@ -81,6 +92,8 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
         if (!grid_sync(gs, &ok))
             return false;
         load_partials<2, kNT>(pt, G, v, red);
+        if constexpr (KIND == kLowRank)
+            lr_gather(lr_part(), G, nlr, lrc);
         ++epoch;
         return true;
     };
@@ -118,7 +131,7 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
         nv[0] = nmax(nv[0], s);
     }
     nv[1] = nv[0];
-    if (!exchange(nv)) {
+    if (!exchange(nv, P.X0)) {
         finish(PHICOMB_EDEVICE, 1);
         return;
     }
@@ -149,14 +162,24 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
         const double step = P.tau / (double)j;
         double mx[2] = {0.0, 0.0};
         for (int64_t row = lo + tid; row < hi; row += kNT) {
-            const RowCtx rc = row_ctx<KIND>(A, row);
+            RowCtx rc{};
+            if constexpr (KIND != kLowRank)
+                rc = row_ctx<KIND>(A, row);
             double tk[R];
 #pragma unroll
             for (int k = 0; k < R; ++k)
                 tk[k] = 0.0;
             for (int i = 0; i < P1; ++i) {
                 double y[1];
-                apply_cols<KIND, 1>(A, rc, Xo, n, i, 0.0, y);
+                if constexpr (KIND == kLowRank) {
+                    // U_row (W^T P_{j-1})[:, i]
+                    const double *ur = A.lr_u + row * A.rank;
+                    y[0] = 0.0;
+                    for (int k = 0; k < A.rank; ++k)
+                        y[0] += ur[k] * lrc[i * A.rank + k];
+                } else {
+                    apply_cols<KIND, 1>(A, rc, Xo, n, i, 0.0, y);
+                }
                 const double x = y[0] * step;
                 Xn[(int64_t)i * n + row] = x;
 #pragma unroll
@@ -174,7 +197,7 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
             mx[0] = nmax(mx[0], st);
             mx[1] = nmax(mx[1], sg);
         }
-        if (!exchange(mx)) {
+        if (!exchange(mx, Xn)) {
             finish(PHICOMB_EDEVICE, j + 1);
             return;
         }
@@ -221,9 +244,9 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
         if (!std::isfinite(beta[k]))
             return PHICOMB_EINVAL;
     const int kind = op->dev.kind;
-    if (kind == kLowRank)
-        return PHICOMB_EINVAL;
-    SeriesFn fn = (kind == kStencil) ? series_r<kStencil>(r) : series_r<kCsr>(r);
+    SeriesFn fn = (kind == kStencil)  ? series_r<kStencil>(r)
+                  : (kind == kLowRank) ? series_r<kLowRank>(r)
+                                       : series_r<kCsr>(r);
     if (!fn)
         return PHICOMB_EINVAL;
     hipStream_t stream = (hipStream_t)stream_;
@@ -232,7 +255,9 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
 
     std::lock_guard<std::mutex> lk(op->mu);
     const size_t sync = (size_t)kSyncBytes + sizeof(double) * 4 * kMaxGrid + 256;
-    const size_t need = sync + sizeof(double) * 2 * (size_t)P1 * (size_t)n;
+    const int rank = op_lr_rank(op);
+    const size_t lr = (rank > 0) ? sizeof(double) * 2 * (size_t)rank * P1 * kMaxGrid + 256 : 0;
+    const size_t need = sync + sizeof(double) * 2 * (size_t)P1 * (size_t)n + lr;
     int st = ensure_workspace(op, need);
     if (st != PHICOMB_OK)
         return st;
@@ -260,6 +285,8 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
     a.info = (int *)(base + kSyncBytes + sizeof(double) * 4 * kMaxGrid);
     a.X0 = (double *)(base + sync);
     a.X1 = a.X0 + (size_t)P1 * n;
+    if (rank > 0)
+        a.lrpart = (double *)(((uintptr_t)(a.X1 + (size_t)P1 * n) + 255) & ~(uintptr_t)255);
     a.V = (const double *)V;
     a.W = (double *)W;
 
@@ -309,7 +336,9 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
         stats->terms_S = info[1];
         stats->status = st;
         // per term: the p+1 columns read and written, W read and written
-        const double opb = (kind == kStencil) ? 0.0 : 12.0 * (double)op->nnz + 4.0 * (n + 1);
+        const double opb = (kind == kStencil)   ? 0.0
+                           : (kind == kLowRank) ? 16.0 * n * rank / P1   // U and W once per term
+                                                : 12.0 * (double)op->nnz + 4.0 * (n + 1);
         stats->bytes_alg = 8.0 * n * (P1 + 2.0 * P1 + r) +
                            (info[1] - 1) * (16.0 * n * P1 + 16.0 * n * r + P1 * opb);
         float ms = 0.0f;
