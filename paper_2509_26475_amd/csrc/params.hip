@@ -26,6 +26,7 @@
 namespace phc {
 
 constexpr int kPNT = 512;          // threads per workgroup
+constexpr int kParamRows = 4;      // rows per thread of the register-cached CSR variant
 constexpr int kPMaxGrid = 4096;
 
 // (scale, ssq) pair: value = scale * sqrt(ssq), scale = max |x| seen.
@@ -125,6 +126,18 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     const int m = P.m;
     const DevOp &A = P.op;
     double *basis = P.basis;
+    // CSR rows of at most kCacheNnz entries, up to kParamRows per thread, stay
+    // in registers for all the powers
+    constexpr bool CACHED = (KIND == kCsrCached);
+    CachedRow crow[CACHED ? kParamRows : 1];
+    if constexpr (CACHED) {
+#pragma unroll
+        for (int q = 0; q < kParamRows; ++q) {
+            const int64_t row = lo + tid + (int64_t)q * kPNT;
+            if (row < hi)
+                load_cached_row(A, row, crow[q]);
+        }
+    }
     auto col = [&](int k) { return basis + (int64_t)k * n; };
     auto finish = [&](double status, double r, double s0, double zs, double fs, double shift,
                       double s, double nfev) {
@@ -269,6 +282,18 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
                     ssq_add(acc, val);
                 }
             }
+        } else if constexpr (CACHED) {
+#pragma unroll
+            for (int q = 0; q < kParamRows; ++q) {
+                const int64_t row = lo + tid + (int64_t)q * kPNT;
+                if (row < hi) {
+                    double w[1];
+                    apply_cached<1>(crow[q], (unsigned)row, x, n, 0, 0.0, w);
+                    const double val = (k == 1) ? w[0] / nv : w[0];   // A (v/||v||)
+                    y[row] = val;
+                    ssq_add(acc, val);
+                }
+            }
         } else {
             for (int64_t row = lo + tid; row < hi; row += kPNT) {
                 const RowCtx rc = row_ctx<KIND>(A, row);
@@ -350,6 +375,16 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
                 sum = wave_sum(sum);
                 if ((tid & 63) == 0)
                     y[row] = sum / s0;
+            }
+        } else if constexpr (CACHED) {
+#pragma unroll
+            for (int q = 0; q < kParamRows; ++q) {
+                const int64_t row = lo + tid + (int64_t)q * kPNT;
+                if (row < hi) {
+                    double w[1];
+                    apply_cached<1>(crow[q], (unsigned)row, x, n, 0, 0.0, w);
+                    y[row] = w[0] / s0;
+                }
             }
         } else {
             for (int64_t row = lo + tid; row < hi; row += kPNT) {
@@ -470,15 +505,20 @@ const void *params_fn(int kind) {
     case kStencil: return (const void *)params_kernel<kStencil>;
     case kDense: return (const void *)params_kernel<kDense>;
     case kLowRank: return (const void *)params_kernel<kLowRank>;
+    case kCsrCached: return (const void *)params_kernel<kCsrCached>;
     default: return (const void *)params_kernel<kCsr>;
     }
 }
 
 int max_params_grid(int kind, int device) {
     static std::mutex mu;
-    static int cached[4][64] = {};
+    static int cached[5][64] = {};
     std::lock_guard<std::mutex> g(mu);
-    int &c = cached[kind == kStencil ? 0 : kind == kDense ? 2 : kind == kLowRank ? 3 : 1][device & 63];
+    int &c = cached[kind == kStencil    ? 0
+                    : kind == kDense    ? 2
+                    : kind == kLowRank  ? 3
+                    : kind == kCsrCached ? 4
+                                         : 1][device & 63];
     if (c > 0)
         return c;
     const void *fn = params_fn(kind);
@@ -555,7 +595,13 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     const int64_t rows_per_wg = (op->dev.kind == kDense) ? 16 : kPNT;
     const int64_t G = std::min<int64_t>(maxg, (n + rows_per_wg - 1) / rows_per_wg);
     const int held = round_xcd(G);   // at most ceil(G/8) of the grid lands on any XCD
-    const void *fn = params_fn(op->dev.kind);
+    // short CSR rows and a chunk of at most kParamRows rows per thread: rows
+    // held in registers (the grid has the same size either way)
+    int kind = op->dev.kind;
+    if (kind == kCsr && op->dev.max_row_nnz <= kCacheNnz &&
+        (n + G - 1) / G <= (int64_t)kParamRows * kPNT && max_params_grid(kCsrCached, op->device) >= G)
+        kind = kCsrCached;
+    const void *fn = params_fn(kind);
     if (cu_acquire(op->device, held, held) != held)
         return PHICOMB_EDEVICE;
     struct Hold {
