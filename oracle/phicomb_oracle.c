@@ -83,9 +83,32 @@ typedef struct {
 
 /* ---------------------------------------------------------------- basics */
 
+/* Inner product sum_i a_i b_i (ascending i) evaluated as if in twice the
+ * working precision: the compensated dot product Dot2 of Ogita, Rump and
+ * Oishi (SIAM J. Sci. Comput. 26, 2005), with the exact product split by
+ * fma and the exact sum split by Knuth's TwoSum.  The result is the exact
+ * inner product rounded once, up to a relative error of order u plus
+ * n^2 u^2 times its condition number, instead of the n u of a plain sum. */
+static double dot2(const double *a, int64_t sa, const double *b, int64_t n)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double p = a[i * sa] * b[i];
+        const double pe = fma(a[i * sa], b[i], -p);   /* p + pe = a_i b_i exactly */
+        const double t = s + p;
+        const double z = t - s;
+        const double te = (s - (t - z)) + (p - z);    /* t + te = s + p exactly */
+        s = t;
+        c += te + pe;
+    }
+    return s + c;
+}
+
 /* y = A x (row sums in stored order).  The low-rank operator of the third
  * experiment (Sec. 5) is applied matrix-free as x -> U (W^T x): first the
- * rank inner products c_k = sum_i W_ik x_i (ascending i), then y_i =
+ * rank inner products c_k = sum_i W_ik x_i, compensated (dot2 above: a row
+ * order plain sum carries an error of n u, which the non-normal cores
+ * amplify beyond the method's own error at the paper's n), then y_i =
  * sum_k U_ik c_k. */
 static void apply_A(const orc_op *A, const double *x, double *y)
 {
@@ -93,12 +116,8 @@ static void apply_A(const orc_op *A, const double *x, double *y)
     if (A->kind == 2) {
         const int r = A->rank;
         double c[16];
-        for (int k = 0; k < r; ++k) {
-            double acc = 0.0;
-            for (int64_t i = 0; i < n; ++i)
-                acc += A->lr_w[i * r + k] * x[i];
-            c[k] = acc;
-        }
+        for (int k = 0; k < r; ++k)
+            c[k] = dot2(A->lr_w + k, r, x, n);
         for (int64_t i = 0; i < n; ++i) {
             double acc = 0.0;
             for (int k = 0; k < r; ++k)
