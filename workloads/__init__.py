@@ -261,19 +261,31 @@ def config3(nside: int = 128, nonnormal: bool = False, tol: float = 1e-12) -> Pr
 
 
 def chebyshev_laplacian(N: int = 100, L: float = 2.0) -> Dense:
-    """Chebyshev spectral collocation of d^2/dx^2 on [0, L] with homogeneous
-    Dirichlet conditions (Sec. 5, second experiment): the first-derivative
-    collocation matrix D on the N+1 Chebyshev points x_j = (cos(pi j/N)+1) L/2
-    (off-diagonal D_ij = (c_i/c_j) (-1)^(i+j) / (x_i - x_j), c_0 = c_N = 2,
-    c_j = 1 otherwise; diagonal = minus the off-diagonal row sum), squared,
-    interior rows and columns kept: A is (N-1) x (N-1), dense, non-normal,
+    """Second-derivative operator on [0, L] with homogeneous Dirichlet
+    conditions by Chebyshev spectral collocation (Sec. 5, second experiment).
+
+    Built from the entrywise definition of the first-derivative collocation
+    matrix on the Chebyshev extreme points xi_k = cos(k pi / N), k = 0..N, of
+    [-1, 1] (Trefethen, Spectral Methods in MATLAB, ch. 6): for k != l,
+        D[k, l] = (w_k / w_l) (-1)^(k+l) / (xi_k - xi_l),
+    with w_0 = w_N = 2 and w_k = 1 otherwise; each diagonal entry is minus
+    the sum of the other entries of its row (D annihilates constants).  The
+    affine map x = (xi + 1) L / 2 scales d/dx = (2/L) d/dxi, so the second
+    derivative is (2/L)^2 D^2; the Dirichlet conditions remove the two
+    boundary rows and columns.  A is (N-1) x (N-1), dense, non-normal, with
     eigenvalues on the negative real axis."""
-    j = np.arange(N + 1)
-    x = (np.cos(np.pi * j / N) + 1.0) * (L / 2.0)
-    c = np.where((j == 0) | (j == N), 2.0, 1.0) * (-1.0) ** j
-    dx = x[:, None] - x[None, :]
-    D = (c[:, None] / c[None, :]) / (dx + np.eye(N + 1))
-    D = D - np.diag(D.sum(axis=1))
+    xi = [math.cos(k * math.pi / N) for k in range(N + 1)]
+    w = [2.0 if k in (0, N) else 1.0 for k in range(N + 1)]
+    D = np.zeros((N + 1, N + 1))
+    for k in range(N + 1):
+        off = 0.0
+        for l in range(N + 1):
+            if l == k:
+                continue
+            sign = -1.0 if (k + l) % 2 else 1.0
+            D[k, l] = (w[k] / w[l]) * sign / (xi[k] - xi[l])
+            off += D[k, l]
+        D[k, k] = -off
     A = (2.0 / L) ** 2 * (D @ D)
     return Dense(np.ascontiguousarray(A[1:N, 1:N]))
 
