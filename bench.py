@@ -6,15 +6,20 @@ parameter selection (Algorithm 1: power basis, objective, Brent) followed
 by the block solve (Algorithm 3) for r abscissae, with the operator and
 the vectors already resident in HBM.
 
-Workload (default): 2-D upwind convection-diffusion on a 512 x 512 grid
-(n = 262144) stored as CSR, velocity (50, 50), p = 3, r = 3,
-t_i = c_i * 1e-4 with c = (1/2, 1/3, 1), beta_ij = c_i^j, v_j ~ N(0,1)
-normalised, tol = 1e-12, FP64.
+Workload (default): 3-D Dirichlet Laplacian, 7-point stencil on a 128^3
+grid (n = 2^21, h = 1/129), p = 2, r = 2, t_i = c_i * 1e-3 with
+c = (1/2, 1), beta_ij = c_i^j, v_j ~ U(-1, 1), tol = 1e-12, FP64: the
+largest single-GPU configuration, whose working set (about 350 MB) exceeds
+the 256 MB Infinity Cache.  --workload selects the others (the 512^2
+convection-diffusion operator is cache resident: its bandwidth is
+effective, not HBM).
 
 Prints one JSON line.  ``roofline`` describes the solve kernel (the
 dominant kernel): algorithmic bytes per launch / its average duration
-measured with HIP events on the launch stream; ``cpu_baseline`` times the
-CPU oracle on one full step of the same workload.
+measured with HIP events on the launch stream; ``traffic`` is the HBM
+traffic per launch from the committed rocprofv3 counter summary when it was
+taken on the current kernel source.  ``cpu_baseline`` times the CPU oracle
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -58,14 +63,43 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(problem, extras: bool = True) -> dict:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(problem, gpu_stats: dict, extras: bool = True) -> dict:
+    """The oracle (single-threaded C) on a bounded sample of the headline
+    step: Algorithm 1 in full, and Algorithm 3 with the same operator,
+    vectors, weights and parameters at t/8 (s_int about 1/8 of the full
+    solve), scaled to the full solve by its column-terms (Taylor terms times
+    block width, S-series and recovery, from the GPU's statistics)."""
     import oracle
+    pr = problem
     t0 = time.perf_counter()
-    W, st, prm = oracle.full(problem)
-    dt = time.perf_counter() - t0
-    out = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-           "sample": "one full step (Algorithm 1 + Algorithm 3) of the same workload, "
-                     f"single-threaded C, {dt:.2f} s"}
+    prm = oracle.params(pr.op, pr.tol, pr.v)
+    t_par = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    _, st = oracle.solve(pr.op, pr.p, pr.r, pr.t / 8.0, pr.beta, pr.V, pr.tol, prm["shift"],
+                         prm["s"])
+    t_smp = time.perf_counter() - t1
+    cS, cR = (pr.p + 1) * pr.r, 2 * pr.r
+    col_smp = (st["terms_S"] - 1) * cS + st["terms_rec"] * cR
+    col_full = (gpu_stats["terms_S"] - 1) * cS + gpu_stats["terms_rec"] * cR
+    t_solve = t_smp * col_full / max(1, col_smp)
+    out = {"value": 1.0 / (t_par + t_solve), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": (f"Algorithm 1 in full ({t_par:.1f} s) and Algorithm 3 at t/8 "
+                      f"(s_int {st['s_int']}, {st['terms_S']}+{st['terms_rec']} terms, "
+                      f"{t_smp:.1f} s) scaled by column-terms to the full solve "
+                      f"({gpu_stats['terms_S']}+{gpu_stats['terms_rec']} terms: {t_solve:.1f} s); "
+                      "single-threaded C"),
+           "cpu_model": _cpu_model(), "host_cores": len(os.sched_getaffinity(0))}
     if extras:
         out["others"] = cpu_baseline_others(oracle)
     return out
@@ -216,7 +250,7 @@ def bench_exp3(pc, wl, torch) -> dict:
     tests."""
     cases = [("M1", 0.1), ("M1", 1.0), ("M1", 10.0), ("M1", 50.0), ("M1", 100.0),
              ("M2", 0.1), ("M2", 1.0), ("M2", 10.0), ("M2", 50.0), ("M2", 100.0),
-             ("M3", 1e-5), ("M3", 1e-3)]
+             ("M3", 1e-5), ("M3", 1e-3), ("M3", 0.1), ("M3", 1.0), ("M3", 10.0)]
     out = {"workload": "low-rank A = U W^T (DCT-II U, W = U M^T); M1 n=2e5 p=3, "
                        "M2 n=4e5 p=4, M3 n=5e5 p=2; alpha=1, tol 2^-53",
            "core": [], "t": [], "params_ms": [], "solve_ms": [], "total_ms": [], "s_int": []}
@@ -359,11 +393,31 @@ def bench_spmm(pc, wl, torch) -> dict:
     return out
 
 
-def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dict:
+def _served_reference(job):
+    """Exact result of one sampled served request (run in a worker process):
+    stencils (Dirichlet Laplacians) by the DST-I eigen-decomposition closed
+    form, dense operators by scipy's expm_multiply (Al-Mohy & Higham 2011)
+    on the augmented matrix of Theorem 1, one abscissa at a time."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import refs
+    op, t, beta, V, W = job
+    if op.kind == "stencil":
+        ref = refs.dst_laplacian(op, t, beta, V)
+    else:
+        ref = refs.expm_multiply_dense_aug(op.A, t, beta, V)
+    return float(refs.rel2_cols(W, ref).max())
+
+
+def bench_served(pc, wl, torch, duration: float, rate: float, slots: int,
+                 sample_frac: float = 0.02, capacity_window: float = 10.0) -> dict:
     """Poisson request stream over a resident operator pool (70 % 2-D/3-D
     stencils n ~ logU[4096, 2^20], 30 % dense nonnormal n in 256..2048),
     p ~ U{1..4}, r ~ U{1..3}, tol 1e-6 (mixed; dense FP64) or 1e-10 (FP64).
-    Latency = completion seen by polling - scheduled arrival."""
+    Latency = completion seen by polling - scheduled arrival.  A seeded
+    sample of the requests (sample_frac) is checked against exact
+    references after the stream.  Capacity: the requests of the stream's
+    first capacity_window seconds submitted at once, completions per second."""
     import numpy as np
     ops, reqs = wl.config5_stream(duration_s=duration, rate=rate)
     handles = [pc.Operator(o) for o in ops]
@@ -374,48 +428,109 @@ def bench_served(pc, wl, torch, duration: float, rate: float, slots: int) -> dic
             prms[(i, tol)] = pc.phicomb_params(h.h, tol, 61, None, 1)
     pc.phicomb_serve_config(0, slots)
     gen = torch.Generator(device="cuda")
-    lat, pending, kernel_ms = [], [], []
+    pick = np.random.default_rng(20250).uniform(size=len(reqs)) < sample_frac
+
+    def make(q):
+        op = ops[q["op_index"]]
+        p, r = q["p"], q["r"]
+        t = (np.arange(1, r + 1) / r) * q["gamma"] / norms[q["op_index"]]
+        gen.manual_seed(q["seed"])
+        V = torch.randn((op.n, p + 1), generator=gen, dtype=torch.float64, device="cuda")
+        W = torch.empty((op.n, r), dtype=torch.float64, device="cuda")
+        prec = pc.MIXED if (q["tol"] == 1e-6 and op.kind != "dense") else pc.FP64
+        return op, t, V, W, prec
+
+    def submit(q, t, V, W, prec):
+        return pc.phicomb_submit(handles[q["op_index"]].h, prms[(q["op_index"], q["tol"])],
+                                 q["p"], q["r"], t, np.ones((q["r"], q["p"] + 1)), V, q["tol"],
+                                 prec, W)
+
+    lat, pending, kernel_ms, sampled = [], [], [], []
     i, n_done = 0, 0
     t0 = time.perf_counter()
     while i < len(reqs) or pending:
         now = time.perf_counter() - t0
         while i < len(reqs) and reqs[i]["arrival"] <= now:
             q = reqs[i]
-            op = ops[q["op_index"]]
-            p, r = q["p"], q["r"]
-            t = (np.arange(1, r + 1) / r) * q["gamma"] / norms[q["op_index"]]
-            gen.manual_seed(q["seed"])
-            V = torch.randn((op.n, p + 1), generator=gen, dtype=torch.float64, device="cuda")
-            W = torch.empty((op.n, r), dtype=torch.float64, device="cuda")
+            op, t, V, W, prec = make(q)
             torch.cuda.current_stream().synchronize()
-            prec = pc.MIXED if (q["tol"] == 1e-6 and op.kind != "dense") else pc.FP64
-            tk = pc.phicomb_submit(handles[q["op_index"]].h, prms[(q["op_index"], q["tol"])],
-                                   p, r, t, np.ones((r, p + 1)), V, q["tol"], prec, W)
-            pending.append((tk, q["arrival"], V, W))
+            tk = submit(q, t, V, W, prec)
+            pending.append((tk, q["arrival"], V, W, i, t))
             i += 1
         still = []
-        for tk, arr, V, W in pending:
+        for tk, arr, V, W, k, t in pending:
             st, stats = pc.phicomb_poll(tk)
             if st == pc.PENDING:
-                still.append((tk, arr, V, W))
+                still.append((tk, arr, V, W, k, t))
                 continue
             if st != pc.OK:
                 raise RuntimeError(f"served request failed: {pc.phicomb_strerror(st)}")
             lat.append(time.perf_counter() - t0 - arr)
             kernel_ms.append(stats.ms)
             n_done += 1
+            if pick[k]:
+                sampled.append((k, t, V.cpu().numpy(), W.cpu().numpy()))
         pending = still
         if pending or i < len(reqs):
             time.sleep(0.0002)
     wall = time.perf_counter() - t0
+    print(f"[bench] served stream: {n_done} requests in {wall:.1f} s", file=sys.stderr,
+          flush=True)
+
+    # capacity: the first capacity_window seconds of the stream, all at once
+    first = [q for q in reqs if q["arrival"] < capacity_window]
+    inflight = [make(q) for q in first]
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    tks = [submit(q, t, V, W, prec) for q, (op, t, V, W, prec) in zip(first, inflight)]
+    left = list(tks)
+    while left:
+        nxt = []
+        for tk in left:
+            st, _ = pc.phicomb_poll(tk)
+            if st == pc.PENDING:
+                nxt.append(tk)
+            elif st != pc.OK:
+                raise RuntimeError(f"capacity request failed: {pc.phicomb_strerror(st)}")
+        left = nxt
+        if left:
+            time.sleep(0.0002)
+    cap_wall = time.perf_counter() - tc
+    del inflight
     for h in handles:
         h.close()
+
+    # the seeded sample against exact references, in worker processes
+    from concurrent.futures import ProcessPoolExecutor
+    jobs = []
+    for k, t, V, W in sampled:
+        q = reqs[k]
+        jobs.append((ops[q["op_index"]], t, np.ones((q["r"], q["p"] + 1)), V, W))
+    tv = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        errs = list(ex.map(_served_reference, jobs))
+    worst = {"stencil_tol1e-6": 0.0, "stencil_tol1e-10": 0.0, "dense_tol1e-6": 0.0,
+             "dense_tol1e-10": 0.0}
+    bad = 0
+    for (k, _, _, _), e in zip(sampled, errs):
+        q = reqs[k]
+        key = f"{ops[q['op_index']].kind}_tol{q['tol']:.0e}".replace("e-0", "e-")
+        worst[key] = max(worst[key], e)
+        bad += int(e > max(10.0 * q["tol"], 1e-12))
+    print(f"[bench] served sample of {len(jobs)} checked in {time.perf_counter() - tv:.1f} s",
+          file=sys.stderr, flush=True)
     lat_ms = 1e3 * np.asarray(lat)
     return {"workload": f"poisson {rate:g}/s x {duration:g} s, 64 stencil + 32 dense ops",
             "requests": n_done, "slots": slots, "p50_ms": float(np.percentile(lat_ms, 50)),
             "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
-            "throughput_req_per_s": n_done / wall,
-            "mean_kernel_ms": float(np.mean(kernel_ms))}
+            "offered_req_per_s": len(reqs) / duration,
+            "completed_req_per_s": n_done / wall,
+            "capacity_req_per_s": len(first) / cap_wall,
+            "capacity_requests": len(first),
+            "mean_kernel_ms": float(np.mean(kernel_ms)),
+            "verified": {"sample": len(jobs), "fraction": sample_frac,
+                         "over_bar": bad, "bar": "max(10 tol, 1e-12) relative 2-norm per column",
+                         "worst_rel_err": worst}}
 
 
 def dense_workload(wl):
@@ -432,21 +547,90 @@ def dense_workload(wl):
                       wl.params_vector(op.n, 1))
 
 
+WORKLOADS = {
+    # name: (description, builder)
+    "lap3d128": ("7-point Dirichlet Laplacian 128^3 (stencil), FP64",
+                 lambda wl: wl.config3(tol=1e-12)),
+    "lap3d128-nonnormal": ("7-point Laplacian 128^3 + 100 on the superdiagonal (stencil), FP64",
+                           lambda wl: wl.config3(nonnormal=True, tol=1e-12)),
+    "convdiff512-csr": ("csr 5-point upwind convection-diffusion 512x512 (cache resident)",
+                        lambda wl: wl.config2(as_csr=True)),
+    "convdiff512-stencil": ("stencil 5-point upwind convection-diffusion 512x512 "
+                            "(cache resident)", lambda wl: wl.config2(as_csr=False)),
+    "dense2048": ("dense upper-triangular non-normal 2048x2048 (MFMA)", None),
+}
+
+
+def _workload_name(key: str, pr) -> str:
+    tol = f"tol{pr.tol:.0e}".replace("e-0", "e-")
+    return {"lap3d128": f"lap3d_128_stencil_p2_r2_{tol}",
+            "lap3d128-nonnormal": f"lap3d_128_nonnormal_stencil_p2_r2_{tol}",
+            "convdiff512-csr": f"convdiff2d_512_csr_p3_r3_{tol}",
+            "convdiff512-stencil": f"convdiff2d_512_stencil_p3_r3_{tol}",
+            "dense2048": f"dense_upper_nonnormal_2048_p3_r3_{tol}"}[key]
+
+
+def timed_steps(pc, torch, pr, steps: int, warmup: int):
+    """Warm-up, then `steps` timed steps (Algorithm 1 + Algorithm 3) bracketed
+    by device synchronisations; returns (seconds, per-step stats, params
+    seconds, last parameters)."""
+    op = pc.Operator(pr.op)
+    V = torch.from_numpy(pr.V).cuda()
+    W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
+        pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
+    torch.cuda.synchronize()
+    stats, t_par = [], 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
+        b = time.perf_counter()
+        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
+        t_par += b - a
+        stats.append(st.as_dict())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    op.close()
+    return dt, stats, t_par, prm
+
+
+def bench_convdiff_effective(pc, wl, torch) -> dict:
+    """The 512^2 convection-diffusion operator (CSR and stencil, p = 3, r = 3,
+    tol 1e-12): its ~50 MB working set stays in the 256 MB Infinity Cache, so
+    the bandwidth here is effective (algorithmic bytes / kernel time), not
+    HBM bandwidth."""
+    import numpy as np
+    out = {"note": "cache-resident working set: effective bandwidth, not HBM"}
+    for key in ("convdiff512-csr", "convdiff512-stencil"):
+        pr = WORKLOADS[key][1](wl)
+        dt, stats, t_par, _ = timed_steps(pc, torch, pr, 10, 2)
+        ms = float(np.mean([s["ms"] for s in stats]))
+        byt = float(np.mean([s["bytes_alg"] for s in stats]))
+        out[key] = {"workload": _workload_name(key, pr), "steps_per_s": 10 / dt,
+                    "solve_kernel_ms": ms, "effective_GBps": byt / (ms * 1e-3) / 1e9,
+                    "s_int": stats[-1]["s_int"], "terms_S": stats[-1]["terms_S"],
+                    "terms_rec": stats[-1]["terms_rec"]}
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--kind", choices=["csr", "stencil", "dense"], default="csr",
-                    help="operator of the headline workload; 'dense' runs the dense "
-                         "non-normal n = 2048 operator of the served stream instead")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="lap3d128",
+                    help="headline workload (default: the 128^3 Laplacian at tol 1e-12)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision and served-stream measurements")
+                    help="skip the extra sections (mixed precision, batched, experiments, "
+                         "block product, served stream)")
     ap.add_argument("--extras", default=None,
                     help="comma-separated subset of the extra sections to run (mixed_tol1e-6, "
-                         "batched, exp2, exp3, exp4, series, spmm, served); default all")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+                         "convdiff512, batched, exp2, exp3, exp4, series, spmm, served); "
+                         "default all")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -475,41 +659,17 @@ def main(argv=None) -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.kind == "dense":
-        pr = dense_workload(wl)
-    else:
-        pr = wl.config2(as_csr=(args.kind == "csr"))
-    op = pc.Operator(pr.op)
-    V = torch.from_numpy(pr.V).cuda()
-    W = torch.empty((pr.n, pr.r), dtype=torch.float64, device="cuda")
-
-    def step():
-        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
-        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
-        return prm, st
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats = []
-    t_par = 0.0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        prm = pc.phicomb_params(op.h, pr.tol, 61, None, 1)
-        b = time.perf_counter()
-        st = pc.phicomb_solve(op.h, prm, pr.p, pr.r, pr.t, pr.beta, V, pr.tol, pc.FP64, W)
-        t_par += b - a
-        stats.append(st.as_dict())
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    desc, builder = WORKLOADS[args.workload]
+    pr = dense_workload(wl) if builder is None else builder(wl)
+    t_start = time.perf_counter()
+    dt, stats, t_par, prm = timed_steps(pc, torch, pr, args.steps, args.warmup)
     value = args.steps / dt
     ms_kernel = float(np.mean([s["ms"] for s in stats]))
     bytes_launch = float(np.mean([s["bytes_alg"] for s in stats]))
     achieved = bytes_launch / (ms_kernel * 1e-3) / 1e9
-    kernel_name = f"solve_kernel<{args.kind},r={pr.r}>"
-    workload = (f"convdiff2d_512_{args.kind}_p3_r3_tol1e-12" if args.kind != "dense"
-                else "dense_upper_nonnormal_2048_p3_r3_tol1e-10")
+    kind = pr.op.kind
+    kernel_name = f"solve_kernel<{kind},r={pr.r}>"
+    workload = _workload_name(args.workload, pr)
     traffic = measured_traffic(kernel_name, workload)
     line = {
         "metric": METRIC,
@@ -524,30 +684,30 @@ def main(argv=None) -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "n": pr.n, "p": pr.p, "r": pr.r,
-                   "operator": (f"{args.kind} 5-point upwind convection-diffusion 512x512"
-                                if args.kind != "dense" else
-                                "dense upper-triangular non-normal 2048x2048 (MFMA)"),
+        "config": {"workload": workload, "n": pr.n, "p": pr.p, "r": pr.r, "operator": desc,
                    "tol": pr.tol, "step": "Algorithm 1 + Algorithm 3"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": kernel_name,
-                     "bytes_per_launch": bytes_launch, "ms_per_launch": ms_kernel},
+                     "bytes_per_launch": bytes_launch, "ms_per_launch": ms_kernel,
+                     "traffic_GBps": (None if traffic is None
+                                      else traffic / (ms_kernel * 1e-3) / 1e9)},
         "solve_only_per_s": 1e3 / ms_kernel,
         "params_ms": 1e3 * t_par / args.steps,
         "s_int": stats[-1]["s_int"], "terms_S": stats[-1]["terms_S"],
         "terms_rec": stats[-1]["terms_rec"],
         "shift": prm.shift, "s": prm.s,
     }
-    op.close()
 
-    def progress(what, t_start):
-        print(f"[bench] {what} done in {time.perf_counter() - t_start:.1f} s", file=sys.stderr,
+    def progress(what, t0):
+        print(f"[bench] {what} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
 
-    progress("headline workload", t0)
+    progress("headline workload", t_start)
     sections = [
         ("mixed_tol1e-6", "mixed precision", lambda: bench_mixed(pc, wl, torch, reps=5)),
+        ("convdiff512", "convection-diffusion 512^2 (effective)",
+         lambda: bench_convdiff_effective(pc, wl, torch)),
         ("batched", "batched", lambda: bench_batched(pc, wl, torch, reps=1)),
         ("exp2", "second experiment", lambda: bench_exp2(pc, wl, torch)),
         ("exp3", "third experiment", lambda: bench_exp3(pc, wl, torch)),
@@ -568,7 +728,9 @@ def main(argv=None) -> int:
             line[key] = fn()
             progress(what, t1)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(pr, extras=not args.no_extras)
+        t1 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(pr, stats[-1], extras=not args.no_extras)
+        progress("cpu baseline", t1)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -48,13 +48,13 @@ extern "C" {
 
 /* precision of the Taylor terms (the parameter search is always FP64) */
 #define PHICOMB_FP64 0
-/* Mixed: in the recovery steps after the first, once the previous Taylor
- * term's block norm is below tol / (80 u32) (u32 = 2^-24) of the smaller of
- * the partial sum and the step's starting block, later terms and their
- * products with A are FP32.  The S-series, the first recovery step, partial
- * sums, the stopping test and everything carried from one step to the next
- * stay FP64, so the result agrees with FP64 to about 10 tol in the block
- * norm.  Terms stay FP64 when the partial sum is outside [1e-20,
+/* Mixed: in every Taylor loop (the S-series and each recovery step), once
+ * the previous term's block norm is below tol / (80 u32) (u32 = 2^-24) of
+ * the smaller of the partial sum and the loop's starting block, later terms
+ * and their products with A are FP32 (an FP64 head and an FP32 tail).
+ * Partial sums, the stopping test and everything carried from one loop to
+ * the next stay FP64, so the result agrees with FP64 to about 10 tol in the
+ * block norm.  Terms stay FP64 when the partial sum is outside [1e-20,
  * 1e30 / (||A||_inf + |xi|)] (FP32 range).  Shapes with no mixed kernel run
  * FP64. */
 #define PHICOMB_MIXED 1
@@ -63,6 +63,7 @@ extern "C" {
 #define PHICOMB_MAX_P 7  /* p <= 7 */
 #define PHICOMB_MAX_R 4  /* r <= 4 */
 #define PHICOMB_MAX_M 100
+#define PHICOMB_MAX_N (1 << 28)  /* rows of an operator (columns are addressed with 32-bit byte offsets) */
 
 typedef struct phicomb_op_s *phicomb_op;
 typedef struct phicomb_req_s *phicomb_req;
@@ -90,7 +91,7 @@ typedef struct {
     int32_t terms_rec;      /* Taylor terms summed over the s_int-1 recovery steps */
     int32_t max_terms_step; /* largest term count of one recovery step */
     int32_t status;
-    int32_t fp32_terms;     /* mixed precision: recovery terms evaluated in FP32 */
+    int32_t fp32_terms;     /* mixed precision: Taylor terms evaluated in FP32 (S-series and recovery) */
     double bytes_alg;       /* algorithmic HBM bytes of the solve (see design notes) */
     double ms;              /* device time of the solve kernel, milliseconds */
 } phicomb_stats_t;
@@ -103,8 +104,8 @@ typedef struct {
  */
 
 /* CSR matrix, host arrays: rowptr[n+1] (rowptr[0] = 0, non-decreasing),
- * col[nnz] in [0, n), val[nnz].  n >= 1, nnz < 2^31.  EINVAL on a malformed
- * structure or a non-finite value. */
+ * col[nnz] in [0, n), val[nnz].  1 <= n <= PHICOMB_MAX_N, nnz < 2^31.  EINVAL
+ * on a malformed structure, a non-finite value or n out of range. */
 int phicomb_op_create_csr(int64_t n, const int32_t *rowptr, const int32_t *col,
                           const double *val, phicomb_op *out);
 
@@ -113,7 +114,7 @@ int phicomb_op_create_csr(int64_t n, const int32_t *rowptr, const int32_t *col,
  * ny*z).  coef[7] = {centre, -x, +x, -y, +y, -z, +z} neighbour weights;
  * superdiag is added to every matrix entry (i, i+1), i < n-1 (a non-normal
  * perturbation; at the end of a grid line it is a new entry).  n = nx*ny*nz
- * must be < 2^31. */
+ * must be <= PHICOMB_MAX_N (EINVAL otherwise). */
 int phicomb_op_create_stencil(int dim, const int32_t grid[3], const double coef[7],
                               double superdiag, phicomb_op *out);
 
@@ -123,7 +124,8 @@ int phicomb_op_create_dense(int64_t n, const double *A, phicomb_op *out);
 /* Low-rank operator A = U W^T (Sec. 5, third experiment: a fixed orthonormal
  * basis U and W = U M^T for a small core M), applied matrix-free as
  * x -> U (W^T x) with O(n rank) work per product.  U and W: host arrays,
- * row-major n x rank, copied to the device.  1 <= rank <= 16, n < 2^31;
+ * row-major n x rank, copied to the device.  1 <= rank <= 16,
+ * 1 <= n <= PHICOMB_MAX_N;
  * a solve additionally needs rank * max((p+1) r + r, 2r) <= 256 (EINVAL
  * otherwise).  The batched entry points do not take this kind (EINVAL).
  * EINVAL on a bad size or a non-finite entry. */
@@ -163,7 +165,10 @@ int phicomb_params(phicomb_op op, double tol, int m, const double *v, uint64_t s
  *   stream    hipStream_t or NULL.
  *   stats     optional, may be NULL.
  * p = 0 returns exp(t_i A) v_0; v_0 = 0 returns sum_{j>=1} beta_ij phi_j v_j.
- * Errors: EINVAL, ENOCONV, ENOMEM, EDEVICE (W then undefined). */
+ * Errors: EINVAL, ENOCONV, ENOMEM,
+ * EDEVICE (W then undefined).  Non-finite entries of V (or weighted columns
+ * beyond the double range) are found by the device in its first pass over V,
+ * before any Taylor term, and reported as EINVAL. */
 int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r,
                   const double *t, const double *beta, const void *V, double tol,
                   int precision, void *W, void *stream, phicomb_stats_t *stats);
@@ -204,10 +209,12 @@ int64_t phicomb_request_bytes(int64_t n, int p, int r, int precision);
  * Many independent solves (Sec. 4, Algorithm 3 each) of uneven size in one
  * persistent launch.  The library splits the launch into groups of
  * workgroups, each running an ordered list of the instances, with group sizes
- * and lists chosen from a cost model of one Taylor term and the expected term
- * count of every instance (s_int steps of the length tol implies), so that
- * the predicted finishing time of the last group is smallest.  The launch is
- * captured once into a HIP graph and replayed by every run.
+ * (and with them the rows each thread owns) and lists chosen from a cost
+ * model of one Taylor term (phicomb_batch_model) and the expected term count
+ * of every instance (s_int steps of the length tol implies), so that the
+ * predicted finishing time of the last group is smallest.  The launch is
+ * captured into a HIP graph and replayed by every run (recaptured when a
+ * refit of the model changes the schedule).
  *   items     [count] solves: same fields as phicomb_solve; every operator of
  *             the kind stencil or CSR (dense operators are CSR inside), all of
  *             one kind and on the current device.  t and beta are copied at
@@ -242,6 +249,22 @@ int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats);
 /* The plan's schedule: number of groups, workgroups of the launch, and the
  * cost model's predicted duration (milliseconds). */
 int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *predicted_ms);
+
+/* The plan's cost model of one Taylor term on G workgroups, in microseconds:
+ *   (G = 1 ? m[0] : m[1] + m[2] G) + ceil(n / (512 G)) (m[3] + m[4] 2r),
+ * an exchange latency plus the rounds of rows each thread works through one
+ * after another.  Every successful run refits it by least squares from the
+ * device clocks of its instances and rebuilds the schedule when the refit
+ * predicts a makespan 10 % below the measured one.  get (optional, 5 doubles)
+ * receives the current model; set (optional, 5 non-negative doubles, e.g. a
+ * model saved from an earlier plan by an autotuner) replaces it and rebuilds
+ * the schedule (EINVAL for a negative or non-finite value). */
+int phicomb_batch_model(phicomb_batch b, double *get, const double *set);
+
+/* The last run's launch time, the model's prediction for that run's plan
+ * before the refit (with the run's measured term counts), and after it. */
+int phicomb_batch_fit(phicomb_batch b, double *measured_ms, double *predicted_ms_before,
+                      double *predicted_ms_after);
 
 int phicomb_batch_destroy(phicomb_batch b);
 
@@ -295,7 +318,7 @@ typedef struct {
     int32_t max_s_int;      /* largest scaling count of any call */
     int32_t status;
     int64_t terms;          /* Taylor terms over all calls (S-series + recovery) */
-    int64_t fp32_terms;     /* mixed precision: recovery terms evaluated in FP32 */
+    int64_t fp32_terms;     /* mixed precision: Taylor terms evaluated in FP32 */
     double ms;              /* device time of the whole integration, milliseconds */
 } phicomb_exprk_stats_t;
 

@@ -4,8 +4,11 @@ Plain, slow, single-threaded IEEE-double C (``phicomb_oracle.c``) following
 Algorithms 1-3 of Al-Mohy, "Computing Linear Combinations of phi-Function
 Actions for Exponential Integrators" (arXiv 2509.26475), step by step.
 Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
-``bench.py`` may import this package; the HIP library never does, and the
-two share no code.
+``bench.py`` may import this package; the HIP library never does, and
+neither includes, links or calls the other.  Two published routines that
+both sides must compute exactly (the correctly rounded binomial coefficient
+and Brent's localmin) are written separately on each side and pinned here
+on their own.
 
 Blocks cross this wrapper row-major ([n][p+1] for V, [n][r] for W) to match
 the library's layout; the C code works column-major internally, so the

@@ -98,6 +98,8 @@ def _lib():
             "phicomb_batch_run": ([P, P, P], I32),
             "phicomb_batch_info": ([P, P, P, P], I32),
             "phicomb_batch_destroy": ([P], I32),
+            "phicomb_batch_model": ([P, P, P], I32),
+            "phicomb_batch_fit": ([P, P, P, P], I32),
             "phicomb_exprk4s6": ([P, P, P, D, I32, D, I32, P, P, P], I32),
             "phicomb_solve_series": ([P, I32, I32, P, P, P, D, P, P, P], I32),
             "phicomb_op_apply": ([P, P, I32, D, P, P, P], I32),
@@ -316,6 +318,27 @@ def phicomb_batch_run(b, count: int, stream=None):
     stats = (StatsT * count)()
     st = _lib().phicomb_batch_run(b, _stream_ptr(stream), stats)
     return st, list(stats)
+
+
+def phicomb_batch_model(b, new=None) -> list:
+    """The plan's cost-model constants (5 doubles); with new, replace them
+    (the schedule is rebuilt) and return the new ones."""
+    out = (C.c_double * 5)()
+    if new is not None:
+        arr = (C.c_double * 5)(*[float(x) for x in new])
+        _check(_lib().phicomb_batch_model(b, None, arr), "phicomb_batch_model")
+    _check(_lib().phicomb_batch_model(b, out, None), "phicomb_batch_model")
+    return list(out)
+
+
+def phicomb_batch_fit(b) -> dict:
+    """Last run: measured launch ms and the model's prediction before and
+    after its refit."""
+    m, p0, p1 = C.c_double(), C.c_double(), C.c_double()
+    _check(_lib().phicomb_batch_fit(b, C.byref(m), C.byref(p0), C.byref(p1)),
+           "phicomb_batch_fit")
+    return {"measured_ms": m.value, "predicted_ms_before": p0.value,
+            "predicted_ms_after": p1.value}
 
 
 def phicomb_batch_info(b) -> dict:

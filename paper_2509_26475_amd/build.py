@@ -14,7 +14,12 @@ LIB = os.path.join(HERE, "libphicomb.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "serve.cpp", "params.hip", "solve.hip", "solve_lowrank.hip", "batch.hip", "exprk.hip", "series.hip", "apply.hip"]
+# the solve and batched kernels are split per operator kind so that they
+# compile in parallel (the largest units first)
+SOURCES = ["batch_stencil.hip", "batch_csr.hip", "solve_stencil.hip", "solve_csr.hip",
+           "solve_csr_cached.hip", "solve_lowrank.hip", "solve_dense.hip", "params.hip",
+           "series.hip", "apply.hip", "exprk.hip", "solve.hip", "batch.hip", "api.cpp",
+           "serve.cpp"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
@@ -40,10 +45,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8) -> str:
+def _stale(src: str) -> bool:
+    """The object of src is missing or older than src or any header."""
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(d, f) for d in (CSRC, INCLUDE)
+                                         for f in os.listdir(d) if f.endswith(".h")]
+    return any(os.path.getmtime(p) > t for p in deps)
+
+
+def build(jobs: int = 8, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental, those whose object is
+    older than the source or a header) and link libphicomb.so."""
     os.makedirs(OBJDIR, exist_ok=True)
+    todo = [s for s in SOURCES if not incremental or _stale(s)]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -54,4 +74,4 @@ def build(jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(incremental="--incremental" in sys.argv))

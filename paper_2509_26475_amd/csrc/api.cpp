@@ -153,6 +153,23 @@ void cu_release(int device, int n) {
     l.cv.notify_all();
 }
 
+int solve_check_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+                     const double *beta, const void *V, double tol, int precision, void *W) {
+    if (!op || !prm || !t || !beta || !V || !W)
+        return PHICOMB_EINVAL;
+    if (p < 0 || p > PHICOMB_MAX_P || r < 1 || r > PHICOMB_MAX_R)
+        return PHICOMB_EINVAL;
+    if (!(tol > 0.0) || !std::isfinite(tol) || prm->status != PHICOMB_OK)
+        return PHICOMB_EINVAL;
+    if (!std::isfinite(prm->shift) || !std::isfinite(prm->s) || prm->s < 0.0)
+        return PHICOMB_EINVAL;
+    if (!finite_array(t, r) || !finite_array(beta, (int64_t)r * (p + 1)))
+        return PHICOMB_EINVAL;
+    if (precision != PHICOMB_FP64 && precision != PHICOMB_MIXED)
+        return PHICOMB_EINVAL;
+    return PHICOMB_OK;
+}
+
 int ensure_workspace(phicomb_op op, size_t bytes) {
     if (op->ws.bytes >= bytes)
         return PHICOMB_OK;
@@ -173,7 +190,7 @@ extern "C" {
 
 int phicomb_op_create_csr(int64_t n, const int32_t *rowptr, const int32_t *col,
                           const double *val, phicomb_op *out) {
-    if (!out || n < 1 || n >= INT32_MAX || !rowptr || !col || !val)
+    if (!out || n < 1 || n > kMaxRows || !rowptr || !col || !val)
         return PHICOMB_EINVAL;
     *out = nullptr;
     if (rowptr[0] != 0)
@@ -210,7 +227,7 @@ int phicomb_op_create_stencil(int dim, const int32_t grid[3], const double coef[
     if (nx < 1 || ny < 1 || nz < 1)
         return PHICOMB_EINVAL;
     const int64_t n = nx * ny * nz;
-    if (n >= INT32_MAX)
+    if (n > kMaxRows)
         return PHICOMB_EINVAL;
     if (!finite_array(coef, 7) || !std::isfinite(superdiag))
         return PHICOMB_EINVAL;
@@ -276,7 +293,7 @@ int phicomb_op_create_dense(int64_t n, const double *A, phicomb_op *out) {
 
 int phicomb_op_create_lowrank(int64_t n, int rank, const double *U, const double *W,
                               phicomb_op *out) {
-    if (!out || n < 1 || n >= INT32_MAX || rank < 1 || rank > kLrRankMax || !U || !W)
+    if (!out || n < 1 || n > kMaxRows || rank < 1 || rank > kLrRankMax || !U || !W)
         return PHICOMB_EINVAL;
     *out = nullptr;
     if (!finite_array(U, n * rank) || !finite_array(W, n * rank))
@@ -347,17 +364,7 @@ int phicomb_params(phicomb_op op, double tol, int m, const double *v, uint64_t s
 int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
                   const double *beta, const void *V, double tol, int precision, void *W,
                   void *stream, phicomb_stats_t *stats) {
-    if (!op || !prm || !t || !beta || !V || !W)
-        return PHICOMB_EINVAL;
-    if (p < 0 || p > PHICOMB_MAX_P || r < 1 || r > PHICOMB_MAX_R)
-        return PHICOMB_EINVAL;
-    if (!(tol > 0.0) || !std::isfinite(tol) || prm->status != PHICOMB_OK)
-        return PHICOMB_EINVAL;
-    if (!std::isfinite(prm->shift) || !std::isfinite(prm->s) || prm->s < 0.0)
-        return PHICOMB_EINVAL;
-    if (!finite_array(t, r) || !finite_array(beta, (int64_t)r * (p + 1)))
-        return PHICOMB_EINVAL;
-    if (precision != PHICOMB_FP64 && precision != PHICOMB_MIXED)
+    if (solve_check_args(op, prm, p, r, t, beta, V, tol, precision, W) != PHICOMB_OK)
         return PHICOMB_EINVAL;
     std::lock_guard<std::mutex> g(op->mu);
     const size_t need = solve_workspace_bytes(op->dev.n, p, r, precision, op_lr_rank(op));

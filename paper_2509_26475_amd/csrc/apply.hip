@@ -6,8 +6,10 @@
 // contiguous range of rows (neighbouring rows of a stencil or banded CSR
 // operator then share an L2).  Up to 16 columns are done by a kernel of that
 // exact width; wider blocks in compile-time chunks of NC, so that a CSR row's
-// indices and values are read once per chunk.  X and Y are column-major
-// (column c at X + c n).
+// indices and values are read once per chunk.  Stencils with an even grid
+// line run one pair of rows per thread instead (16-byte loads and stores,
+// x-neighbours across lanes): 4.9 against 3.6 TB/s at 6 columns on the 128^3
+// grid.  X and Y are column-major (column c at X + c n).
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -56,7 +58,38 @@ __global__ __launch_bounds__(kANT) void apply_kernel_exact(DevOp A, const double
         Y[(int64_t)j * n + row] = y[j];
 }
 
+// Stencil operators with nx even: one lane per pair of consecutive rows
+// (16-byte loads, x-neighbours across lanes; see apply_pair).  Lanes past the
+// end compute a clamped pair and store nothing.
+template <int NC>
+__global__ __launch_bounds__(kANT) void apply_pairs_kernel(DevOp A, const double *__restrict__ X,
+                                                           int, double shift,
+                                                           double *__restrict__ Y) {
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t n = A.n;
+    const int64_t i0 = 2 * ((int64_t)b * kANT + threadIdx.x);
+    const bool act = i0 < n;
+    const PairCtx pc = pair_ctx(A, act ? i0 : n - 2);
+    double y0[NC], y1[NC];
+    apply_pair<NC, double, double>(A, pc, X, n, 0, shift, y0, y1);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            typedef double __attribute__((ext_vector_type(2))) d2;
+            d2 v = {y0[j], y1[j]};
+            *(d2 *)(Y + (int64_t)j * n + i0) = v;
+        }
+    }
+}
+
 using ApplyFn = void (*)(DevOp, const double *, int, double, double *);
+
+template <int... Q>
+static ApplyFn pairs_fn(int ncols, std::integer_sequence<int, Q...>) {
+    ApplyFn fn = nullptr;
+    ((ncols == Q + 1 ? (fn = apply_pairs_kernel<Q + 1>, 0) : 0), ...);
+    return fn;
+}
 
 template <int KIND, int... Q>
 static ApplyFn exact_fn(int ncols, std::integer_sequence<int, Q...>) {
@@ -102,7 +135,12 @@ extern "C" int phicomb_op_apply(phicomb_op op, const void *X, int ncols, double 
     ApplyFn fn = (kind == kStencil) ? apply_fn<kStencil>(ncols) : apply_fn<kCsr>(ncols);
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t n = op->dev.n;
-    const int64_t blocks = (n + kANT - 1) / kANT;
+    int64_t blocks = (n + kANT - 1) / kANT;
+    // stencils with an even grid line and at most 16 columns: row pairs
+    if (kind == kStencil && op->dev.nx % 2 == 0 && ncols <= 16) {
+        fn = pairs_fn(ncols, std::make_integer_sequence<int, 16>{});
+        blocks = (n / 2 + kANT - 1) / kANT;
+    }
     if (blocks > 0x7fffffff)
         return PHICOMB_EINVAL;
     hipEvent_t e0 = nullptr, e1 = nullptr;

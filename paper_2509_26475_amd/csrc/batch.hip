@@ -5,9 +5,9 @@
 // list of instances one after the other, every instance on the group's whole
 // sub-grid with its own barrier area and work blocks, so groups never wait
 // for each other.  The host picks the group sizes and lists from a cost model
-// of one Taylor term (barrier latency plus the term's bytes over the group's
-// CUs) and the expected term count of each instance (s_int steps of the
-// Taylor length that tol implies), minimising the predicted makespan: an
+// of one Taylor term (exchange latency plus the rounds of rows each thread
+// works through) and the expected term count of each instance (s_int steps of
+// the Taylor length that tol implies), minimising the predicted makespan: an
 // instance that alone needs more than the makespan gets a group of several
 // workgroups, the rest are packed longest-first onto single workgroups.
 // The launch (barrier reset and solve kernel) is captured once into a HIP
@@ -15,22 +15,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <numeric>
 #include <vector>
 
-#include "solve_body.h"
+#include "batch_kernel.h"
 
 using namespace phc;
 
 namespace phc {
-
-// Variant of an instance inside the batched kernel: R (1..4) and the row
-// layout (1, 2 or 4 rows per thread with E in registers, or E in memory).
-constexpr int kLayouts = 4;
-constexpr int kLayoutEmem = 3;
 
 // Resets every instance's barrier area and status words (one block each).
 __global__ void batch_sync_init(const SolveArgs *__restrict__ args, int count) {
@@ -44,61 +40,11 @@ __global__ void batch_sync_init(const SolveArgs *__restrict__ args, int count) {
         args[it].info[threadIdx.x] = 0;
 }
 
-template <int KIND, int R, bool MIX>
-__device__ __forceinline__ void run_layout(int layout, const SolveArgs &P, SolveShared &sh,
-                                           unsigned G, unsigned bid) {
-    switch (layout) {
-    case 0: solve_body<KIND, R, 1, false, MIX>(P, sh, G, bid, (int)bid); break;
-    case 1: solve_body<KIND, R, 2, false, MIX>(P, sh, G, bid, (int)bid); break;
-    case 2: solve_body<KIND, R, 4, false, MIX>(P, sh, G, bid, (int)bid); break;
-    default: solve_body<KIND, R, 1, true, MIX>(P, sh, G, bid, (int)bid); break;
-    }
-}
-
-// wg_group[b]: group of workgroup b; gfirst/gsize: first workgroup and size of
-// each group; glist[goff[g] .. goff[g+1]): the instances group g runs, in order.
-// ts[it][0..1]: device wall clock at the start and end of instance it (for
-// the cost model's calibration).
-template <int KIND, bool MIX>
-__global__ __launch_bounds__(kNT) void solve_batch_kernel(const SolveArgs *__restrict__ args,
-                                                          const int *__restrict__ variant,
-                                                          const int *__restrict__ wg_group,
-                                                          const int *__restrict__ gfirst,
-                                                          const int *__restrict__ gsize,
-                                                          const int *__restrict__ goff,
-                                                          const int *__restrict__ glist,
-                                                          long long *__restrict__ ts) {
-    __shared__ SolveShared sh;
-    const int g = wg_group[blockIdx.x];
-    const unsigned G = (unsigned)gsize[g];
-    const unsigned bid = blockIdx.x - (unsigned)gfirst[g];
-    for (int q = goff[g]; q < goff[g + 1]; ++q) {
-        const int it = glist[q];
-        const SolveArgs &P = args[it];
-        const int v = variant[it];
-        const int layout = v % kLayouts;
-        if (bid == 0 && threadIdx.x == 0)
-            ts[2 * it] = wall_clock64();
-        switch (v / kLayouts) {
-        case 0: run_layout<KIND, 1, MIX>(layout, P, sh, G, bid); break;
-        case 1: run_layout<KIND, 2, MIX>(layout, P, sh, G, bid); break;
-        case 2: run_layout<KIND, 3, MIX>(layout, P, sh, G, bid); break;
-        default: run_layout<KIND, 4, MIX>(layout, P, sh, G, bid); break;
-        }
-        if (bid == 0 && threadIdx.x == 0)
-            ts[2 * it + 1] = wall_clock64();
-        __syncthreads();   // the next instance reuses the shared state
-    }
-}
-
-using BatchKernel = void (*)(const SolveArgs *, const int *, const int *, const int *,
-                             const int *, const int *, const int *, long long *);
-
 static BatchKernel pick_batch_kernel(int kind, bool mix) {
     if (kind == kStencil)
-        return mix ? solve_batch_kernel<kStencil, true> : solve_batch_kernel<kStencil, false>;
+        return batch_kernel_stencil(mix);
     if (kind == kCsr)
-        return mix ? solve_batch_kernel<kCsr, true> : solve_batch_kernel<kCsr, false>;
+        return batch_kernel_csr(mix);
     return nullptr;
 }
 
@@ -119,27 +65,35 @@ static double taylor_terms(double tol) {
 
 struct ItemCost {
     double terms;   // Taylor terms over the whole solve
-    double bytes;   // bytes of one term
+    double cols;    // columns of the recovery block (2r)
     int64_t n;
     int gmax;       // most workgroups that still own 512 rows each
 };
 
 // One term on G workgroups, microseconds: the exchange (a workgroup barrier
-// for G = 1, the grid barrier otherwise) plus the term's bytes at a per-CU
-// streaming rate.  The starting constants gave the best measured schedule
-// of the 256-instance benchmark batch on MI355X; the first run of a plan
-// refits them from the measured duration of every instance.
+// for G = 1, the grid barrier otherwise, growing with G) plus the rounds of
+// rows each thread works through one after another, ceil(n / (512 G)), each
+// taking a latency that grows with the block's width.  A term is bound by
+// memory latency per round rather than by bytes per CU at these sizes.  The
+// starting constants are MI355X measurements; every run of a plan refits
+// them from the device clocks of its instances (least squares over the
+// instances), and the autotuner keeps the fitted model on disk.
 struct Model {
-    double e1 = 1.5, bw1 = 25e3;              // G = 1: exchange (us), bytes per us
-    double e2 = 3.0, g2 = 0.006, bw2 = 25e3;  // G > 1
+    double e1 = 1.5;     // single-workgroup exchange (us)
+    double e2 = 3.0;     // grid exchange (us)
+    double g2 = 0.006;   // growth of the grid exchange per workgroup (us)
+    double l0 = 0.6;     // one round of rows (us)
+    double l1 = 0.1;     // one round of rows, per column (us)
 };
 static thread_local Model t_model;
 
+static double rounds(const ItemCost &c, int G) {
+    return std::ceil((double)c.n / ((double)kNT * (double)G));
+}
 static double term_us(const ItemCost &c, int G) {
     const Model &m = t_model;
-    if (G == 1)
-        return m.e1 + c.bytes / m.bw1;
-    return m.e2 + m.g2 * G + c.bytes / ((double)G * m.bw2);
+    const double ex = (G == 1) ? m.e1 : m.e2 + m.g2 * G;
+    return ex + rounds(c, G) * (m.l0 + m.l1 * c.cols);
 }
 static double cost_us(const ItemCost &c, int G) { return c.terms * term_us(c, G); }
 
@@ -262,7 +216,8 @@ struct phicomb_batch_s {
     int kind = 0;
     int precision = 0;
     bool mix = false;
-    bool tuned = false;
+    int runs = 0;                 // runs whose clocks refit the model
+    double last_measured_ms = 0.0, last_predicted_ms = 0.0, refit_predicted_ms = 0.0;
     int cap = 0;                  // workgroups the launch may use
     std::vector<phicomb_op> ops;
     std::vector<int> p, r, s_int;
@@ -360,33 +315,83 @@ int build_plan(phicomb_batch b) {
     return PHICOMB_OK;
 }
 
-// Least-squares fit of a + b x (returns false when degenerate or negative).
-bool fit_line(const std::vector<double> &x, const std::vector<double> &y, double &a, double &b) {
-    const size_t m = x.size();
-    if (m < 3)
+// Least squares for the model's five constants from per-instance samples
+// (features: single workgroup, grid, grid size, rounds, rounds x columns; the
+// measured microseconds per term), by the normal equations with a tiny ridge.
+// Constants of features that no sample exercises keep their old values; the
+// fit is rejected if any fitted constant comes out negative or non-finite.
+bool fit_model(const std::vector<std::array<double, 5>> &x, const std::vector<double> &y,
+               Model &m) {
+    constexpr int K = 5;
+    double a[K][K + 1] = {};
+    bool used[K] = {};
+    for (size_t s = 0; s < x.size(); ++s)
+        for (int i = 0; i < K; ++i) {
+            if (x[s][i] != 0.0)
+                used[i] = true;
+            for (int j = 0; j < K; ++j)
+                a[i][j] += x[s][i] * x[s][j];
+            a[i][K] += x[s][i] * y[s];
+        }
+    if (x.size() < 3)
         return false;
-    double sx = 0, sy = 0, sxx = 0, sxy = 0;
-    for (size_t i = 0; i < m; ++i) {
-        sx += x[i];
-        sy += y[i];
-        sxx += x[i] * x[i];
-        sxy += x[i] * y[i];
+    double tr = 0.0;
+    for (int i = 0; i < K; ++i)
+        tr += a[i][i];
+    for (int i = 0; i < K; ++i)
+        a[i][i] += 1e-9 * tr + (used[i] ? 0.0 : 1.0);
+    for (int c = 0; c < K; ++c) {   // Gaussian elimination with partial pivoting
+        int piv = c;
+        for (int r = c + 1; r < K; ++r)
+            if (std::fabs(a[r][c]) > std::fabs(a[piv][c]))
+                piv = r;
+        if (!(std::fabs(a[piv][c]) > 0.0))
+            return false;
+        for (int j = 0; j <= K; ++j)
+            std::swap(a[c][j], a[piv][j]);
+        for (int r = 0; r < K; ++r) {
+            if (r == c)
+                continue;
+            const double f = a[r][c] / a[c][c];
+            for (int j = c; j <= K; ++j)
+                a[r][j] -= f * a[c][j];
+        }
     }
-    const double det = m * sxx - sx * sx;
-    if (!(det > 0.0))
-        return false;
-    b = (m * sxy - sx * sy) / det;
-    a = (sy - b * sx) / m;
-    return a > 0.0 && b > 0.0;
+    double v[K];
+    for (int i = 0; i < K; ++i) {
+        v[i] = a[i][K] / a[i][i];
+        if (used[i] && !(v[i] >= 0.0 && std::isfinite(v[i])))
+            return false;
+    }
+    Model out = m;
+    if (used[0]) out.e1 = v[0];
+    if (used[1]) out.e2 = v[1];
+    if (used[2]) out.g2 = v[2];
+    if (used[3]) out.l0 = v[3];
+    if (used[4]) out.l1 = v[4];
+    m = out;
+    return true;
 }
 
-// After a run: the measured duration of every instance calibrates the model
-// (per-term time against the term's bytes, single workgroups and grids
-// separately) and the measured term counts replace the estimates; the plan is
-// rebuilt when its predicted makespan beats the measured one by 10 %.
+static double predicted_ms(phicomb_batch b) {
+    t_model = b->model;
+    double pred = 0.0;
+    for (int g = 0; g < b->ng; ++g) {
+        double t = 0.0;
+        for (int it : b->sched.glist[g])
+            t += cost_us(b->cost[it], b->sched.gsize[g]);
+        pred = std::max(pred, t);
+    }
+    return pred * 1e-3;
+}
+
+// After a run: the measured duration of every instance (device clocks) and
+// its measured term count refit the model; the schedule is rebuilt with it
+// when that predicts a makespan 10 % below the run just measured.
 void tune(phicomb_batch b, double measured_ms) {
-    b->tuned = true;
-    std::vector<double> x1, y1, x2, y2;
+    b->runs += 1;
+    std::vector<std::array<double, 5>> x;
+    std::vector<double> y;
     std::vector<int> group_of(b->count, 0);
     for (int g = 0; g < b->ng; ++g)
         for (int it : b->sched.glist[g])
@@ -400,38 +405,18 @@ void tune(phicomb_batch b, double measured_ms) {
         if (!(us > 0.0))
             continue;
         const int G = b->sched.gsize[group_of[it]];
-        if (G == 1) {
-            x1.push_back(b->cost[it].bytes);
-            y1.push_back(us / terms);
-        } else {
-            x2.push_back(b->cost[it].bytes / G);
-            y2.push_back(us / terms - b->model.g2 * G);
-        }
+        const double rr = rounds(b->cost[it], G);
+        x.push_back({G == 1 ? 1.0 : 0.0, G > 1 ? 1.0 : 0.0, G > 1 ? (double)G : 0.0, rr,
+                     rr * b->cost[it].cols});
+        y.push_back(us / terms);
     }
-    double a, c;
-    if (fit_line(x1, y1, a, c)) {
-        b->model.e1 = a;
-        b->model.bw1 = 1.0 / c;
-    }
-    if (fit_line(x2, y2, a, c)) {
-        b->model.e2 = a;
-        b->model.bw2 = 1.0 / c;
-    }
-    // adopt the refit only if it reproduces the run just measured
+    b->last_measured_ms = measured_ms;
+    b->last_predicted_ms = predicted_ms(b);   // this run's plan, term counts now measured
+    Model m = b->model;
+    if (fit_model(x, y, m))
+        b->model = m;
+    b->refit_predicted_ms = predicted_ms(b);
     t_model = b->model;
-    double pred = 0.0;
-    for (int g = 0; g < b->ng; ++g) {
-        double t = 0.0;
-        for (int it : b->sched.glist[g])
-            t += cost_us(b->cost[it], b->sched.gsize[g]);
-        pred = std::max(pred, t);
-    }
-    pred *= 1e-3;
-    if (!(pred > 0.75 * measured_ms && pred < 1.25 * measured_ms)) {
-        b->model = Model();
-        t_model = b->model;
-        return;
-    }
     const Schedule trial = make_schedule(b->cost, b->cap);
     if (trial.makespan * 1e-3 < 0.9 * measured_ms)
         build_plan(b);
@@ -508,9 +493,8 @@ int phicomb_batch_create(int count, const phicomb_batch_item *items, int precisi
         }
         const double steps = std::max(1.0, sc);
         const double k = taylor_terms(q.tol);
-        const double opb = (q.op->dev.kind != kStencil) ? 12.0 * q.op->nnz / (double)n : 0.0;
         b->cost[i].terms = k * steps;
-        b->cost[i].bytes = (double)n * (24.0 * 2 * q.r + opb);
+        b->cost[i].cols = 2.0 * q.r;
         b->cost[i].n = n;
         b->cost[i].gmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + kNT - 1) / kNT));
         b->ops[i] = q.op;
@@ -664,13 +648,13 @@ int phicomb_batch_run(phicomb_batch b, void *stream, phicomb_stats_t *stats) {
             o.terms_S = info[1];
             o.terms_rec = info[2];
             o.max_terms_step = info[3];
-            o.fp32_terms = info[4];
+            o.fp32_terms = info[4] + info[5];
             o.status = info[0];
             o.bytes_alg = solve_algorithmic_bytes(b->ops[i], b->p[i], b->r[i], b->s_int[i], info);
             o.ms = ms;
         }
     }
-    if (!b->tuned && worst == PHICOMB_OK)
+    if (worst == PHICOMB_OK)
         tune(b, ms);
     return worst;
 }
@@ -684,6 +668,39 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
         *workgroups = b->wgs;
     if (predicted_ms)
         *predicted_ms = b->sched.makespan * 1e-3;
+    return PHICOMB_OK;
+}
+
+int phicomb_batch_model(phicomb_batch b, double *get, const double *set) {
+    if (!b)
+        return PHICOMB_EINVAL;
+    if (get) {
+        get[0] = b->model.e1;
+        get[1] = b->model.e2;
+        get[2] = b->model.g2;
+        get[3] = b->model.l0;
+        get[4] = b->model.l1;
+    }
+    if (set) {
+        for (int i = 0; i < 5; ++i)
+            if (!(set[i] >= 0.0) || !std::isfinite(set[i]))
+                return PHICOMB_EINVAL;
+        b->model = Model{set[0], set[1], set[2], set[3], set[4]};
+        return build_plan(b);
+    }
+    return PHICOMB_OK;
+}
+
+int phicomb_batch_fit(phicomb_batch b, double *measured_ms, double *predicted_ms_before,
+                      double *predicted_ms_after) {
+    if (!b)
+        return PHICOMB_EINVAL;
+    if (measured_ms)
+        *measured_ms = b->last_measured_ms;
+    if (predicted_ms_before)
+        *predicted_ms_before = b->last_predicted_ms;
+    if (predicted_ms_after)
+        *predicted_ms_after = b->refit_predicted_ms;
     return PHICOMB_OK;
 }
 

@@ -116,7 +116,7 @@ __global__ void exprk_fold(const int *__restrict__ info, long long *acc) {
         if (acc[0] == 0 && info[0] != 0)
             acc[0] = info[0];
         acc[1] += (long long)info[1] + info[2];
-        acc[2] += info[4];
+        acc[2] += info[4] + info[5];
         acc[3] += 1;
     }
 }
@@ -187,7 +187,8 @@ extern "C" int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, cons
     const unsigned grid = (unsigned)((n + kENT - 1) / kENT);
 
     // workgroup slots for every solve of the integration, held until the end
-    const int want = (int)std::min<int64_t>(device_cus(op->device), (n + kNT - 1) / kNT);
+    int want = 0, need_g = 0;
+    solve_grid_request(op, &want, &need_g);
     const int slots = cu_acquire(op->device, want, want);
     if (slots < 1)
         return PHICOMB_EDEVICE;

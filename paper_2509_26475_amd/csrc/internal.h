@@ -28,6 +28,9 @@ enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2, kCsrCached = 3, kLowRank
 // Low-rank operators A = U W^T: rank at most kLrRankMax.
 constexpr int kLrRankMax = 16;
 constexpr int kCacheNnz = 8;   // CSR rows up to this length can live in registers
+// Largest operator: work-block columns are addressed with 32-bit byte offsets
+// (ld_col), which hold FP64 columns of up to 2^29 rows; one power of two to spare.
+constexpr int64_t kMaxRows = PHICOMB_MAX_N;
 
 // Operator as seen by the kernels (passed by value).
 struct DevOp {
@@ -67,6 +70,44 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// ------------------------------------------------- compensated inner products
+// Inner products over all n rows (W^T x of a low-rank operator) are carried as
+// unevaluated pairs hi + lo (Dot2 of Ogita, Rump and Oishi, SIAM J. Sci.
+// Comput. 26, 2005): the product's rounding error comes from fma, the sum's
+// from Knuth's TwoSum, and both are kept in lo.  The sum is then as accurate
+// as if it had been formed in twice the working precision and rounded once,
+// independently of the order in which rows, lanes and workgroups are added.
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+    const double s = a.hi + b.hi;
+    const double z = s - a.hi;
+    const double e = (a.hi - (s - z)) + (b.hi - z);   // s + e = a.hi + b.hi exactly
+    return DD{s, e + (a.lo + b.lo)};
+}
+
+// acc += a * b
+__device__ __forceinline__ void dd_fma(DD &acc, double a, double b) {
+    const double p = a * b;
+    const double pe = __builtin_fma(a, b, -p);         // p + pe = a b exactly
+    const double s = acc.hi + p;
+    const double z = s - acc.hi;
+    const double e = (acc.hi - (s - z)) + (p - z);
+    acc.hi = s;
+    acc.lo += e + pe;
+}
+
+__device__ __forceinline__ DD wave_sum_dd(DD v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const DD o{__shfl_xor(v.hi, off, 64), __shfl_xor(v.lo, off, 64)};
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
 // ------------------------------------------------------------ grid barrier
 // Barrier of a cooperative (co-resident) grid, grouped by XCD.
 //
@@ -90,6 +131,7 @@ enum : int {
     kLnGroup = 4,        // 16 group counters
     kLnGroupGen = 20,    // 16 group generations
     kLnGroupSize = 36,   // 16 group sizes
+    kLnMax = 52,         // 3 rotating lines of maxima folded into the barrier
 };
 
 struct GridSync {
@@ -167,7 +209,19 @@ __device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_
     return *ok_lds != 0;
 }
 
-__device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
+// Barrier over the grid.  With nv > 0 it also reduces nv non-negative
+// doubles (vals, valid in thread 0: this workgroup's maxima) to their maximum
+// over all workgroups, left in res (LDS, nv entries) for every thread.  The
+// maxima ride on the arrival: each workgroup applies an agent-scope 64-bit
+// atomic max to the line of this barrier (non-negative doubles order like
+// their bit patterns; a NaN, positive or negative, compares above every
+// number, so it wins as in nmax) and waits for it before it arrives; after
+// the barrier one load per value returns the result.  Barrier g uses line
+// kLnMax + g % 3; the last arrival at the top of barrier g clears line
+// (g + 1) % 3, which every workgroup has finished reading (it was last read
+// after barrier g - 2) and nobody writes before passing barrier g.
+__device__ __forceinline__ bool grid_sync_impl(GridSync &gs, int *ok_lds, int nv,
+                                               const double *vals, double *res) {
     wait_own_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -176,6 +230,12 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
         unsigned *bar = gs.bar;
         unsigned *gc = bar + kLineU * (kLnGroup + gs.xcc);
         unsigned *gg = bar + kLineU * (kLnGroupGen + gs.xcc);
+        unsigned long long *line =
+            (unsigned long long *)(bar + kLineU * (kLnMax + g % 3u));
+        for (int j = 0; j < nv; ++j)
+            __hip_atomic_fetch_max(line + j, (unsigned long long)__double_as_longlong(vals[j]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);   // the maxima are performed before the arrival
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         // The counters only ever grow (modulo 2^32): arrival number
         // (g+1)*size - 1 closes generation g.  Nothing is reset, so an early
@@ -186,9 +246,16 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
             l2_writeback();
             const unsigned top = __hip_atomic_fetch_add(bar + kLineU * kLnTop, 1u,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (top + 1u == (g + 1u) * gs.ngroups)
+            if (top + 1u == (g + 1u) * gs.ngroups) {
+                unsigned long long *next =
+                    (unsigned long long *)(bar + kLineU * (kLnMax + (g + 1u) % 3u));
+                for (int j = 0; j < 4; ++j)
+                    __hip_atomic_exchange(next + j, 0ull, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);   // cleared before the generation opens
                 __hip_atomic_fetch_add(bar + kLineU * kLnTopGen, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+            }
             if (!spin_until_ne(bar + kLineU * kLnTopGen, g))
                 ok = 0;
             l2_invalidate();
@@ -198,6 +265,9 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
                 ok = 0;
             l2_invalidate();   // this CU's L1 (and non-coherent L2 lines)
         }
+        for (int j = 0; j < nv; ++j)
+            res[j] = __longlong_as_double((long long)__hip_atomic_load(
+                line + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         gs.gen = g + 1;
         *ok_lds = ok;
     }
@@ -205,31 +275,40 @@ __device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
     return *ok_lds != 0;
 }
 
-// Workgroup max of NV values into part[bid*2 + j] (plain stores, published by
-// the next grid_sync); bid is the workgroup's index within its grid.
+__device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
+    return grid_sync_impl(gs, ok_lds, 0, nullptr, nullptr);
+}
+
+// Maximum of NV non-negative values over the whole grid, left in every
+// thread's v: the workgroup's maximum (wave shuffles, then the waves through
+// red in LDS) is folded into the barrier's arrival (grid_sync_impl).  res:
+// LDS scratch of NV doubles.
 template <int NV, int NT>
-__device__ __forceinline__ void store_partials(double (&v)[NV], double *part, double (*red)[2],
-                                               unsigned bid) {
+__device__ __forceinline__ bool grid_max(GridSync &gs, int *ok_lds, double (&v)[NV],
+                                         double (*red)[2], double *res) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
         v[j] = wave_max(v[j]);
-    __syncthreads();   // every wave has finished reading red from the last exchange
+    __syncthreads();   // every wave has finished reading res from the last exchange
     if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             red[wave][j] = v[j];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    double m[NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            double m = red[0][j];
-            for (int w = 1; w < NT / 64; ++w)
-                m = nmax(m, red[w][j]);
-            part[bid * 2 + j] = m;
-        }
+    for (int j = 0; j < NV; ++j) {
+        m[j] = red[0][j];
+        for (int w = 1; w < NT / 64; ++w)
+            m[j] = nmax(m[j], red[w][j]);
     }
+    const bool ok = grid_sync_impl(gs, ok_lds, NV, m, res);
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = res[j];
+    return ok;
 }
 
 // Max of NV values over one workgroup, left in every thread (a grid of a
@@ -253,39 +332,6 @@ __device__ __forceinline__ void workgroup_max(double (&v)[NV], double (*red)[2])
         for (int w = 1; w < NT / 64; ++w)
             r = nmax(r, red[w][j]);
         v[j] = r;
-    }
-}
-
-// Max over all workgroups' partials, after grid_sync; every thread gets it.
-template <int NV, int NT>
-__device__ __forceinline__ void load_partials(const double *part, unsigned nblocks,
-                                              double (&out)[NV], double (*red)[2]) {
-    double m[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        m[j] = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += NT) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            m[j] = nmax(m[j], part[b * 2 + j]);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        m[j] = wave_max(m[j]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            red[wave][j] = m[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        double r = red[0][j];
-        for (int w = 1; w < NT / 64; ++w)
-            r = nmax(r, red[w][j]);
-        out[j] = r;
     }
 }
 
@@ -445,6 +491,116 @@ __device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
     }
 }
 
+// ------------------------------------------------------ stencil row pairs
+// Rows i0 and i0 + 1 (i0 even) of a stencil product, NC columns, computed by
+// one lane with 8- or 16-byte loads of the pair (float2 / double2).  The
+// x-neighbours outside the pair (i0 - 1 and i0 + 2) belong to the adjacent
+// lanes, which hold the adjacent pairs, and come over by cross-lane moves;
+// only the first and last lane of a wave load theirs.  In linear row order
+// the right neighbour i + 1 is also where the superdiagonal entry (i, i + 1)
+// sits, so the end of a grid line needs no special case.  Requires nx even (a
+// pair never straddles a grid line, n is even and the y and z offsets keep
+// the pair's alignment) and every lane of the wave to take part: a lane past
+// the end computes a clamped pair and its caller does not store it.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct Vec2<float> {
+    typedef float __attribute__((ext_vector_type(2))) type;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type ld_pair(const T *__restrict__ base, unsigned i) {
+    return *(const typename Vec2<T>::type *)((const char *)base + i * (unsigned)sizeof(T));
+}
+
+struct PairCtx {
+    unsigned i0;          // even row of the pair
+    unsigned mask;        // neighbours present: bit0 -y, 1 +y, 2 -z, 3 +z
+    double wl0, wr0;      // row i0: weights of i0 - 1 and i0 + 1
+    double wr1;           // row i0 + 1: weight of i0 + 2
+};
+
+__device__ __forceinline__ PairCtx pair_ctx(const DevOp &A, int64_t i0) {
+    PairCtx pc;
+    const unsigned i = (unsigned)i0;
+    pc.i0 = i;
+    const unsigned nx = (unsigned)A.nx, ny = (unsigned)A.ny;
+    const unsigned x = i % nx, yz = i / nx;
+    const unsigned y = yz % ny, z = yz / ny;
+    unsigned m = 0;
+    m |= (y > 0) ? 1u : 0u;
+    m |= (y + 1 < ny) ? 2u : 0u;
+    if (A.dim == 3) {
+        m |= (z > 0) ? 4u : 0u;
+        m |= (z + 1 < (unsigned)A.nz) ? 8u : 0u;
+    }
+    pc.mask = m;
+    const int64_t n = A.n;
+    pc.wl0 = (x > 0) ? A.c[1] : 0.0;
+    pc.wr0 = A.c[2] + A.superdiag;   // x + 1 < nx always (x even, nx even); i0 + 1 < n
+    pc.wr1 = ((x + 2 < nx) ? A.c[2] : 0.0) + ((i0 + 2 < n) ? A.superdiag : 0.0);
+    return pc;
+}
+
+template <int NC, typename TX, typename TA>
+__device__ __forceinline__ void apply_pair(const DevOp &A, const PairCtx &pc,
+                                           const TX *__restrict__ X, int64_t ld, int col0,
+                                           double shift, TA (&y0)[NC], TA (&y1)[NC]) {
+    const int lane = threadIdx.x & 63;
+    const unsigned i = pc.i0;
+    const unsigned n = (unsigned)A.n;
+    const unsigned sy = (unsigned)A.nx, sz = (unsigned)A.nx * (unsigned)A.ny;
+    const TA cc = (TA)(A.c[0] - shift);
+    const TA wl0 = (TA)pc.wl0, wr0 = (TA)pc.wr0, wl1 = (TA)A.c[1], wr1 = (TA)pc.wr1;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const TX *__restrict__ b = X + (int64_t)(col0 + j) * ld;
+        const auto v = ld_pair(b, i);
+        TX l = __shfl_up(v.y, 1, 64);
+        TX r = __shfl_down(v.x, 1, 64);
+        if (lane == 0)
+            l = (i > 0) ? ld_col(b, i - 1u) : (TX)0;
+        if (lane == 63)
+            r = (i + 2u < n) ? ld_col(b, i + 2u) : (TX)0;
+        // the same terms in the same order as apply_cols (centre, -x, +x,
+        // -y, +y, -z, +z), so that a row's value does not depend on whether
+        // it was computed alone or in a pair
+        TA a0 = cc * (TA)v.x;
+        a0 += wl0 * (TA)l;
+        a0 += wr0 * (TA)v.y;
+        TA a1 = cc * (TA)v.y;
+        a1 += wl1 * (TA)v.x;
+        a1 += wr1 * (TA)r;
+        if (pc.mask & 1u) {
+            const auto w = ld_pair(b, i - sy);
+            a0 += (TA)A.c[3] * (TA)w.x;
+            a1 += (TA)A.c[3] * (TA)w.y;
+        }
+        if (pc.mask & 2u) {
+            const auto w = ld_pair(b, i + sy);
+            a0 += (TA)A.c[4] * (TA)w.x;
+            a1 += (TA)A.c[4] * (TA)w.y;
+        }
+        if (pc.mask & 4u) {
+            const auto w = ld_pair(b, i - sz);
+            a0 += (TA)A.c[5] * (TA)w.x;
+            a1 += (TA)A.c[5] * (TA)w.y;
+        }
+        if (pc.mask & 8u) {
+            const auto w = ld_pair(b, i + sz);
+            a0 += (TA)A.c[6] * (TA)w.x;
+            a1 += (TA)A.c[6] * (TA)w.y;
+        }
+        y0[j] = a0;
+        y1[j] = a1;
+    }
+}
+
 // A CSR row of at most kCacheNnz entries held in registers for a whole
 // solve (the operator never changes between Taylor terms).
 struct CachedRow {
@@ -530,10 +686,16 @@ void cu_release(int device, int n);
 
 // implemented in solve.hip
 // cu_floor: fewest workgroups the solve accepts (0: one per CU up to n/512).
+// events: two events for the kernel's device time, or nullptr to create and
+// destroy a pair for this call.
 int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
               const double *beta, const void *V, double tol, int precision, void *W,
               hipStream_t stream, phicomb_stats_t *stats, void *ws, size_t ws_bytes,
-              double *pinned, int cu_floor = 0);
+              double *pinned, int cu_floor = 0, hipEvent_t *events = nullptr);
+// Workgroups a solve on op asks the slot ledger for (want: one per CU up to
+// one per 512 rows, dense operators one per 32 rows) and the fewest it can
+// run with (floor: dense operators need one per kDenseRows rows).
+void solve_grid_request(phicomb_op op, int *want, int *floor_g);
 // rank > 0: a low-rank operator of that rank (adds the W^T X exchange area)
 size_t solve_workspace_bytes(int64_t n, int p, int r, int precision, int rank = 0);
 // rank of a low-rank operator, 0 for the other kinds
@@ -543,4 +705,8 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
                 hipStream_t stream, phicomb_params_t *out);
 // implemented in api.cpp
 int ensure_workspace(phicomb_op op, size_t bytes);
+// Host-side argument checks of phicomb_solve (sizes, finiteness of t, beta
+// and tol, parameters, precision): PHICOMB_OK or PHICOMB_EINVAL.
+int solve_check_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
+                     const double *beta, const void *V, double tol, int precision, void *W);
 }  // namespace phc

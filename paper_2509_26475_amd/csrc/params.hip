@@ -90,7 +90,7 @@ struct ParamsArgs {
     double *basis;      // [m+1][n]
     unsigned *bar;      // sync area
     double *part;       // [2][kPMaxGrid][2]
-    double *lrpart;     // low rank: [2][kLrRankMax][kPMaxGrid] partial W^T x
+    double *lrpart;     // low rank: [2][hi, lo][kLrRankMax][kPMaxGrid] partial W^T x
     double *out;        // 16 values, see params_fp64
 };
 
@@ -194,27 +194,31 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     // workgroup's partial over its rows, then the sum over all workgroups in
     // index order, the same in every workgroup.
     unsigned lr_epoch = 0;
+    const size_t lr_lo = (size_t)kLrRankMax * kPMaxGrid;   // [2 parities][hi, lo][rank][grid]
     auto lr_dot = [&](const double *x) __attribute__((always_inline)) -> bool {
         __syncthreads();   // this workgroup's rows of x are written
-        double *pt = P.lrpart + (size_t)(lr_epoch & 1) * kLrRankMax * kPMaxGrid;
+        double *pt = P.lrpart + (size_t)(lr_epoch & 1) * 2 * lr_lo;
         const int rank = A.rank;
         for (int k = wave; k < rank; k += kPNT / 64) {
-            double acc = 0.0;
+            DD acc{0.0, 0.0};
             for (int64_t row = lo + lane; row < hi; row += 64)
-                acc += A.lr_w[row * rank + k] * x[row];
-            acc = wave_sum(acc);
-            if (lane == 0)
-                pt[(size_t)k * kPMaxGrid + blockIdx.x] = acc;
+                dd_fma(acc, A.lr_w[row * rank + k], x[row]);
+            acc = wave_sum_dd(acc);
+            if (lane == 0) {
+                pt[(size_t)k * kPMaxGrid + blockIdx.x] = acc.hi;
+                pt[(size_t)k * kPMaxGrid + blockIdx.x + lr_lo] = acc.lo;
+            }
         }
         if (!grid_sync(gs, &ok_lds))
             return false;
         for (int k = wave; k < rank; k += kPNT / 64) {
-            double acc = 0.0;
+            DD acc{0.0, 0.0};
             for (unsigned b = lane; b < G; b += 64)
-                acc += pt[(size_t)k * kPMaxGrid + b];
-            acc = wave_sum(acc);
+                acc = dd_add(acc, DD{pt[(size_t)k * kPMaxGrid + b],
+                                     pt[(size_t)k * kPMaxGrid + b + lr_lo]});
+            acc = wave_sum_dd(acc);
             if (lane == 0)
-                lrc[k] = acc;
+                lrc[k] = acc.hi + acc.lo;
         }
         __syncthreads();
         ++lr_epoch;
@@ -541,7 +545,7 @@ constexpr int kBrentMaxIt = 100;
 size_t params_workspace_bytes(int64_t n, int m) {
     return (size_t)kSyncBytes + sizeof(double) * (4 * kPMaxGrid + 32 + 128) +
            sizeof(double) * (size_t)n * (size_t)(m + 1) +
-           sizeof(double) * 2 * kLrRankMax * kPMaxGrid;
+           sizeof(double) * 4 * kLrRankMax * kPMaxGrid;
 }
 
 int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed,

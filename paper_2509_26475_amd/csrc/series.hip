@@ -33,7 +33,7 @@ struct SeriesArgs {
     double *X0, *X1;                    // [p+1][n] ping-pong
     unsigned *bar;
     double *part;                       // [2][kMaxGrid][2]
-    double *lrpart;                     // low rank: [2][rank (p+1)][kMaxGrid] partial W^T P_j
+    double *lrpart;                     // low rank: [2][hi, lo][rank (p+1)][kMaxGrid] partial W^T P_j
     int *info;                          // status, terms
 };
 
@@ -47,6 +47,7 @@ __global__ void series_sync_init(unsigned *bar, int *info) {
 template <int KIND, int R>
 __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
     __shared__ double red[kNT / 64][2];
+    __shared__ double res[2];
     __shared__ double wk[kRMax][kPMax1];   // this term's weight of P_j[:, i] in column k
     __shared__ double rpow[kRMax];         // (t_k / tau)^j
     __shared__ double lrc[kLrVals];        // low rank: W^T P_j of the coming product
@@ -75,25 +76,23 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
     // low rank (A = U W^T): the pass that writes P_j also leaves this
     // workgroup's partial W^T P_j, summed by every workgroup after the exchange
     const int nlr = (KIND == kLowRank) ? A.rank * P1 : 0;
-    auto lr_part = [&]() { return P.lrpart + (size_t)(epoch & 1) * nlr * kMaxGrid; };
+    const size_t lr_lo = (size_t)nlr * kMaxGrid;
+    auto lr_part = [&]() { return P.lrpart + (size_t)(epoch & 1) * 2 * lr_lo; };
     auto exchange = [&](double (&v)[2], const double *Xw) -> bool {
         if constexpr (KIND == kLowRank)
-            lr_publish(A, n, lo, hi, Xw, P1, 0, lr_part(), single ? 0u : bid);
+            lr_publish(A, n, lo, hi, Xw, P1, 0, lr_part(), lr_lo, single ? 0u : bid);
         if (single) {
             wait_own_stores();
             workgroup_max<2, kNT>(v, red);
             if constexpr (KIND == kLowRank)
-                lr_gather(lr_part(), 1, nlr, lrc);
+                lr_gather(lr_part(), lr_lo, 1, nlr, lrc);
             ++epoch;
             return true;
         }
-        double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
-        store_partials<2, kNT>(v, pt, red, bid);
-        if (!grid_sync(gs, &ok))
+        if (!grid_max<2, kNT>(gs, &ok, v, red, res))
             return false;
-        load_partials<2, kNT>(pt, G, v, red);
         if constexpr (KIND == kLowRank)
-            lr_gather(lr_part(), G, nlr, lrc);
+            lr_gather(lr_part(), lr_lo, G, nlr, lrc);
         ++epoch;
         return true;
     };
@@ -256,7 +255,7 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
     std::lock_guard<std::mutex> lk(op->mu);
     const size_t sync = (size_t)kSyncBytes + sizeof(double) * 4 * kMaxGrid + 256;
     const int rank = op_lr_rank(op);
-    const size_t lr = (rank > 0) ? sizeof(double) * 2 * (size_t)rank * P1 * kMaxGrid + 256 : 0;
+    const size_t lr = (rank > 0) ? sizeof(double) * 4 * (size_t)rank * P1 * kMaxGrid + 256 : 0;
     const size_t need = sync + sizeof(double) * 2 * (size_t)P1 * (size_t)n + lr;
     int st = ensure_workspace(op, need);
     if (st != PHICOMB_OK)

@@ -21,30 +21,36 @@ static KernelFn pick_kernel(int kind, int r, int rpt, bool emem, bool mix) {
     if (kind == kLowRank)
         return pick_lowrank(r, rpt, emem, mix);
     if (kind == kStencil)
-        return pick_r<kStencil>(r, rpt, emem, mix);
+        return pick_stencil(r, rpt, emem, mix);
     if (kind == kCsr)
-        return pick_r<kCsr>(r, rpt, emem, mix);
+        return pick_csr(r, rpt, emem, mix);
     if (kind == kCsrCached && !emem)
-        return pick_r<kCsrCached>(r, rpt, false, mix);
+        return pick_csr_cached(r, rpt, mix);
     return nullptr;
 }
 
-static int max_coresident(KernelFn fn, int device) {
+// Co-resident workgroups of a kernel on a device (occupancy x CUs), cached in
+// a fixed table (no allocation after the first query of a kernel).
+static int max_coresident(KernelFn fn, int device, int nt = kNT) {
+    struct Entry {
+        void *fn;
+        int device, total;
+    };
+    constexpr int kCache = 512;
     static std::mutex m;
-    static std::vector<std::pair<std::pair<void *, int>, int>> cache;
+    static Entry cache[kCache];
+    static int used = 0;
     std::lock_guard<std::mutex> g(m);
-    for (auto &e : cache)
-        if (e.first.first == (void *)fn && e.first.second == device)
-            return e.second;
+    for (int i = 0; i < used; ++i)
+        if (cache[i].fn == (void *)fn && cache[i].device == device)
+            return cache[i].total;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, kNT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, nt, 0) !=
         hipSuccess)
         return 0;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
-        return 0;
-    const int total = std::min(per_cu * prop.multiProcessorCount, kMaxGrid);
-    cache.push_back({{(void *)fn, device}, total});
+    const int total = std::min(per_cu * device_cus(device), kMaxGrid);
+    if (used < kCache)
+        cache[used++] = Entry{(void *)fn, device, total};
     return total;
 }
 
@@ -59,8 +65,8 @@ static int64_t lr_values(int p, int r, int rank) {
 
 size_t solve_workspace_bytes(int64_t n, int p, int r, int precision, int rank) {
     const int64_t cS = (int64_t)(p + 1) * r, cR = 2LL * r, cW = std::max(cS, cR);
-    const size_t f32 = (precision == PHICOMB_MIXED) ? (size_t)4 * n * 2 * cR + 256 : 0;
-    const size_t lr = (rank > 0) ? (size_t)8 * 2 * lr_values(p, r, rank) * kMaxGrid + 256 : 0;
+    const size_t f32 = (precision == PHICOMB_MIXED) ? (size_t)4 * n * 2 * cW + 256 : 0;
+    const size_t lr = (rank > 0) ? (size_t)8 * 4 * lr_values(p, r, rank) * kMaxGrid + 256 : 0;
     return sync_bytes() + (size_t)8 * (size_t)n * (size_t)(cS + 2 * cW + cR) + f32 + lr;
 }
 
@@ -71,7 +77,8 @@ size_t solve_workspace_bytes(int64_t n, int p, int r, int precision, int rank) {
 // Mixed precision: an FP32 term reads and writes its term block in 4-byte
 // words (8 n c bytes fewer per term).
 static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, int r,
-                                int terms_S, int terms_rec, int s_int, int f32_rec) {
+                                int terms_S, int terms_rec, int s_int, int f32_rec,
+                                int f32_S) {
     const double w = 8.0, N = (double)n;
     const double cS = (double)(p + 1) * r, cR = 2.0 * r;
     const double opb = (op.kind == kCsr)       ? (12.0 * (double)nnz + 4.0 * (N + 1))
@@ -84,7 +91,7 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
     b += terms_rec * (4 * w * N * cR + opb);                            // recovery terms
     b += (s_int - 1) * (w * N * p * r + 2 * w * N * cR);                // step epilogues
     b += 3 * w * N * r;                                                 // combine
-    b -= 8.0 * N * f32_rec * cR;                                         // FP32 term blocks
+    b -= 8.0 * N * (f32_rec * cR + f32_S * cS);                          // FP32 term blocks
     return b;
 }
 
@@ -96,25 +103,32 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
 // private frame with no scratch traffic in their code (up to kFrameOk
 // bytes); spilling ones have hundreds.
 constexpr size_t kFrameOk = 64;
-template <int R>
-static KernelFn dense_kernel() { return solve_kernel<kDense, R, 1, true, false>; }
 
 // Dense operators: at most kDenseRows rows per workgroup (one workgroup up to
 // n = kDenseRows), else 32 rows per workgroup so that the k range of every
 // row tile is split over the waves; FP64 only.
 static int64_t dense_grid(int64_t n) { return n <= kDenseRows ? 1 : (n + 31) / 32; }
 
-static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_needed1, int cap,
-                               int64_t *G) {
+void solve_grid_request(phicomb_op op, int *want, int *floor_g) {
+    const int64_t n = op->dev.n;
+    const int cus = device_cus(op->device);
     if (op->dev.kind == kDense) {
-        KernelFn f = nullptr;
-        switch (r) {
-        case 1: f = dense_kernel<1>(); break;
-        case 2: f = dense_kernel<2>(); break;
-        case 3: f = dense_kernel<3>(); break;
-        case 4: f = dense_kernel<4>(); break;
-        default: return nullptr;
-        }
+        *want = (int)std::min<int64_t>(cus, dense_grid(n));
+        // at most kDenseRows rows per workgroup
+        *floor_g = (int)std::min<int64_t>(*want, (n + kDenseRows - 1) / kDenseRows);
+    } else {
+        *want = (int)std::min<int64_t>(cus, (n + kNT - 1) / kNT);
+        *floor_g = 1;
+    }
+}
+
+static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_needed1, int cap,
+                               int64_t *G, int *nt) {
+    *nt = kNT;
+    if (op->dev.kind == kDense) {
+        KernelFn f = pick_dense(r);
+        if (!f)
+            return nullptr;
         const int maxg = std::min(max_coresident(f, op->device), cap);
         if (maxg < 1)
             return nullptr;
@@ -146,6 +160,23 @@ static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_neede
             }
         }
     }
+    // E in memory.  Stencils with an even grid line: the 1024-thread kernel
+    // (16 waves per CU keep twice the loads in flight of the 512-thread one)
+    if (op->dev.kind == kStencil && op->dev.nx % 2 == 0) {
+        for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
+            KernelFn f = pick_stencil_wide(r, mix && pass == 0);
+            hipFuncAttributes fa;
+            if (!f || hipFuncGetAttributes(&fa, (const void *)f) != hipSuccess ||
+                fa.localSizeBytes > kFrameOk)
+                continue;
+            const int maxg = std::min(max_coresident(f, op->device, kWideNT), cap);
+            if (maxg < 1)
+                continue;
+            *G = std::min<int64_t>(maxg, (op->dev.n + kWideNT - 1) / kWideNT);
+            *nt = kWideNT;
+            return f;
+        }
+    }
     KernelFn f = pick_kernel(op->dev.kind, r, 1, true, mix);
     if (!f)
         return nullptr;
@@ -171,8 +202,6 @@ int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, c
     a.cS = P1 * r;
     a.cR = 2 * r;
     a.kcap = kTermCap;
-    if (const char *cap = getenv("PHICOMB_TERM_CAP"))   // failure-path tests only
-        a.kcap = std::max(2, std::min(kTermCap, atoi(cap)));
     a.tol = tol;
     a.xi = prm->shift;
     double tmax = 0.0;
@@ -213,8 +242,8 @@ int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, c
     if (mix) {
         float *f = (float *)(((uintptr_t)d + 255) & ~(uintptr_t)255);
         a.Uf0 = f;
-        a.Uf1 = f + (size_t)n * a.cR;
-        d = (double *)(a.Uf1 + (size_t)n * a.cR);
+        a.Uf1 = f + (size_t)n * cW;
+        d = (double *)(a.Uf1 + (size_t)n * cW);
     }
     const int rank = (op->dev.kind == kLowRank) ? op->dev.rank : 0;
     if (rank > 0) {
@@ -247,12 +276,13 @@ int solve_launch_held(phicomb_op op, const phicomb_params_t *prm, int p, int r, 
         return st;
     const int64_t wgs_needed1 = (op->dev.n + kNT - 1) / kNT;
     int64_t G = 0;
-    KernelFn fn = select_variant(op, r, precision == PHICOMB_MIXED, wgs_needed1, slots, &G);
+    int nt = kNT;
+    KernelFn fn = select_variant(op, r, precision == PHICOMB_MIXED, wgs_needed1, slots, &G, &nt);
     if (!fn)
         return PHICOMB_EINVAL;
     solve_sync_init<<<1, 256, 0, stream>>>(a.bar, a.info);
     void *args[] = {&a};
-    if (launch_persistent((const void *)fn, (unsigned)G, kNT, args, stream) != hipSuccess)
+    if (launch_persistent((const void *)fn, (unsigned)G, nt, args, stream) != hipSuccess)
         return PHICOMB_EDEVICE;
     *info_dev = a.info;
     *s_int = a.s_int;
@@ -260,13 +290,14 @@ int solve_launch_held(phicomb_op op, const phicomb_params_t *prm, int p, int r, 
 }
 
 double solve_algorithmic_bytes(phicomb_op op, int p, int r, int s_int, const int *info) {
-    return algorithmic_bytes(op->dev, op->nnz, op->dev.n, p, r, info[1], info[2], s_int, info[4]);
+    return algorithmic_bytes(op->dev, op->nnz, op->dev.n, p, r, info[1], info[2], s_int, info[4],
+                             info[5]);
 }
 
 int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const double *t,
               const double *beta, const void *V, double tol, int precision, void *W,
               hipStream_t stream, phicomb_stats_t *stats, void *ws, size_t ws_bytes,
-              double *pinned, int cu_floor) {
+              double *pinned, int cu_floor, hipEvent_t *events) {
     const bool mix = (precision == PHICOMB_MIXED);
     const int64_t n = op->dev.n;
     SolveArgs a;
@@ -278,19 +309,17 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
     }
     const int s_int = a.s_int;
     const int64_t wgs_needed1 = (n + kNT - 1) / kNT;
-    const int cus = device_cus(op->device);
     // Persistent launches on one device draw workgroup slots from a shared
     // ledger so that concurrent solves never exceed co-residency together.
-    const bool dense = (op->dev.kind == kDense);
-    const int want = (int)std::min<int64_t>(cus, dense ? dense_grid(n) : wgs_needed1);
-    int floor_g = (cu_floor > 0) ? std::min(want, cu_floor) : want;
-    if (dense)   // at most kDenseRows rows per workgroup
-        floor_g = std::max<int>(floor_g, (int)std::min<int64_t>(want, (n + kDenseRows - 1) / kDenseRows));
+    int want = 0, need_g = 0;
+    solve_grid_request(op, &want, &need_g);
+    const int floor_g = std::max((cu_floor > 0) ? std::min(want, cu_floor) : want, need_g);
     const int granted = cu_acquire(op->device, want, floor_g);
     if (granted < 1)
         return PHICOMB_EDEVICE;
     int64_t G = 0;
-    KernelFn fn = select_variant(op, r, mix, wgs_needed1, granted, &G);
+    int nt = kNT;
+    KernelFn fn = select_variant(op, r, mix, wgs_needed1, granted, &G, &nt);
     if (!fn) {
         cu_release(op->device, granted);
         return PHICOMB_EINVAL;
@@ -304,24 +333,39 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
         ~Hold() { cu_release(dev, g); }
     } hold{op->device, held};
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool timed = (hipEventCreate(&e0) == hipSuccess) && (hipEventCreate(&e1) == hipSuccess);
+    const bool own_events = (events == nullptr);
+    bool timed;
+    if (own_events) {
+        timed = (hipEventCreate(&e0) == hipSuccess) && (hipEventCreate(&e1) == hipSuccess);
+    } else {
+        e0 = events[0];
+        e1 = events[1];
+        timed = true;
+    }
+    auto drop_events = [&]() {
+        if (own_events) {
+            if (e0)
+                hipEventDestroy(e0);
+            if (e1)
+                hipEventDestroy(e1);
+        }
+    };
     solve_sync_init<<<1, 256, 0, stream>>>(a.bar, a.info);
     if (timed)
         hipEventRecord(e0, stream);
     void *args[] = {&a};
-    hipError_t le = launch_persistent((const void *)fn, (unsigned)G, kNT, args, stream);
+    hipError_t le = launch_persistent((const void *)fn, (unsigned)G, nt, args, stream);
     if (le != hipSuccess) {
-        if (timed) {
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-        }
+        drop_events();
         return PHICOMB_EDEVICE;
     }
     if (timed)
         hipEventRecord(e1, stream);
     hipMemcpyAsync(pinned, a.info, 8 * sizeof(int), hipMemcpyDeviceToHost, stream);
-    if (hipStreamSynchronize(stream) != hipSuccess)
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        drop_events();
         return PHICOMB_EDEVICE;
+    }
     const int *info = (const int *)pinned;
     const int st = info[0];
     if (stats) {
@@ -330,18 +374,15 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
         stats->terms_S = info[1];
         stats->terms_rec = info[2];
         stats->max_terms_step = info[3];
-        stats->fp32_terms = info[4];
+        stats->fp32_terms = info[4] + info[5];
         stats->status = st;
         stats->bytes_alg = algorithmic_bytes(op->dev, op->nnz, n, p, r, info[1], info[2], s_int,
-                                             info[4]);
+                                             info[4], info[5]);
         float ms = 0.0f;
         if (timed && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
             stats->ms = ms;
     }
-    if (timed) {
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-    }
+    drop_events();
     return st;
 }
 

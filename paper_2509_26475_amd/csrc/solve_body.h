@@ -43,6 +43,8 @@
 namespace phc {
 
 constexpr int kNT = 512;           // threads per workgroup of the solve kernel (8 waves)
+constexpr int kWideNT = 1024;      // the E-in-memory stencil kernel (16 waves, see pick_wide)
+constexpr int kMaxNT = 1024;
 constexpr int kMaxGrid = 4096;     // partial-maximum slots per parity
 constexpr int kLrVals = 256;       // entries of W^T X exchanged per term at most
 
@@ -60,12 +62,12 @@ struct SolveArgs {
     const double *V;                    // [n][p+1] row-major (caller)
     double *W;                          // [n][r]  row-major (caller)
     double *S, *U0, *U1, *E;
-    float *Uf0, *Uf1;                   // FP32 recovery term blocks [cR][n] (mixed precision)
+    float *Uf0, *Uf1;                   // FP32 term blocks [max(cS, cR)][n] (mixed precision)
     double mix_tau;                     // tol / (10 u_fp32): FP32 term threshold
     double mix_lo, mix_hi;              // partial-sum norms for which FP32 terms are safe
     unsigned *bar;                      // sync area (kSyncBytes)
     double *part;                       // [2][kMaxGrid][2] partial maxima
-    double *lrpart;                     // low rank: [2][lrv][kMaxGrid] partial W^T X
+    double *lrpart;                     // low rank: [2][2][lrv][kMaxGrid] partial W^T X (hi, lo)
     int lrv;                            // low rank: rank * max(cS + r, 2r)
     int *info;                          // status, terms_S, terms_rec, max_terms_step
 };
@@ -80,16 +82,16 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // Visit the rows this thread owns.  Register-resident layout: RPT rows at
-// stride kNT inside the workgroup's contiguous chunk, visited with a
+// stride NT inside the workgroup's contiguous chunk, visited with a
 // compile-time index q; memory layout: a grid-stride loop over the chunk.
-template <int RPT, bool EMEM, class F>
+template <int RPT, bool EMEM, int NT, class F>
 __device__ __forceinline__ void for_rows(int64_t lo, int64_t hi, F &&f) {
     if constexpr (EMEM) {
-        for (int64_t row = lo + threadIdx.x; row < hi; row += kNT)
+        for (int64_t row = lo + threadIdx.x; row < hi; row += NT)
             f(row, std::integral_constant<int, 0>{});
     } else {
         static_for<RPT>([&](auto q) {
-            unsigned r32 = (unsigned)(lo + threadIdx.x) + (unsigned)(decltype(q)::value * kNT);
+            unsigned r32 = (unsigned)(lo + threadIdx.x) + (unsigned)(decltype(q)::value * NT);
             // opaque to the optimiser: addresses derived from the row are
             // rebuilt inside every Taylor term instead of being hoisted out
             // of the term loop and kept live for all RPT rows
@@ -104,15 +106,15 @@ __device__ __forceinline__ void for_rows(int64_t lo, int64_t hi, F &&f) {
     }
 }
 
-// Mixed precision (MIX): in the recovery steps after the first, a Taylor
-// term is computed and stored in FP32 once the previous term is small enough
-// that FP32 rounding of the new one stays below tol/10 of the step's result
-// (an FP64 head then an FP32 tail).  The reference for "the step's result" is
-// the smaller of the partial sum and the step's starting block: partial sums
-// of a rough block swell through cancellation before they settle, so they
-// alone would let FP32 in too early.  The S-series and the first recovery
-// step (whose input carries the rough components of V) stay FP64, as do the
-// partial sums, the stopping test and everything carried across steps.
+// Mixed precision (MIX): in every Taylor loop (the S-series and each
+// recovery step) a term is computed and stored in FP32 once the previous
+// term is small enough that FP32 rounding of the new one stays below tol/10
+// of the loop's result (an FP64 head then an FP32 tail).  The reference for
+// "the loop's result" is the smaller of the partial sum and the loop's
+// starting block: partial sums of a rough block swell through cancellation
+// before they settle, so they alone would let FP32 in too early.  The
+// partial sums, the stopping test and everything carried from one loop to
+// the next stay FP64.
 constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predecessor
 
 // ------------------------------------------------------------ dense operator
@@ -183,57 +185,86 @@ __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, in
 
 // ------------------------------------------------------- low-rank operator
 // This workgroup's partial sums of W^T X over its rows [lo, hi) for columns
-// c < ncols of X (column-major, leading dimension n), stored value-major at
-// out[(voff + c rank + k) kMaxGrid + bid]: one wave per value, lanes over
-// the rows, a fixed shuffle tree.  The block was written by this workgroup.
+// c < ncols of X (column-major, leading dimension n), as compensated pairs
+// stored value-major: hi at out[(voff + c rank + k) kMaxGrid + bid], lo at
+// the same index plus lo_off.  One wave per value, lanes over the rows, a
+// fixed shuffle tree.  The block was written by this workgroup.
 template <class TX>
 __device__ __forceinline__ void lr_publish(const DevOp &A, int64_t n, int64_t lo, int64_t hi,
                                            const TX *__restrict__ X, int ncols, int voff,
-                                           double *__restrict__ out, unsigned bid) {
+                                           double *__restrict__ out, size_t lo_off,
+                                           unsigned bid) {
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = A.rank;
     for (int v = wave; v < ncols * rank; v += kNT / 64) {
         const int c = v / rank, k = v % rank;
         const TX *xc = X + (int64_t)c * n;
-        double acc = 0.0;
+        DD acc{0.0, 0.0};
         for (int64_t row = lo + lane; row < hi; row += 64)
-            acc += A.lr_w[row * rank + k] * (double)xc[row];
-        acc = wave_sum(acc);
-        if (lane == 0)
-            out[(size_t)(voff + v) * kMaxGrid + bid] = acc;
+            dd_fma(acc, A.lr_w[row * rank + k], (double)xc[row]);
+        acc = wave_sum_dd(acc);
+        if (lane == 0) {
+            const size_t o = (size_t)(voff + v) * kMaxGrid + bid;
+            out[o] = acc.hi;
+            out[o + lo_off] = acc.lo;
+        }
     }
 }
 
-// W^T X = the sum of all G workgroups' partials, in the same order in every
-// workgroup: one wave per value, lanes over the workgroups, a fixed tree.
-__device__ __forceinline__ void lr_gather(const double *__restrict__ part, unsigned G, int nv,
-                                          double *lrc) {
+// W^T X = the sum of all G workgroups' partial pairs, in the same order in
+// every workgroup: one wave per value, lanes over the workgroups, a fixed
+// tree, rounded once at the end.
+__device__ __forceinline__ void lr_gather(const double *__restrict__ part, size_t lo_off,
+                                          unsigned G, int nv, double *lrc) {
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int v = wave; v < nv; v += kNT / 64) {
-        double acc = 0.0;
-        for (unsigned g = lane; g < G; g += 64)
-            acc += part[(size_t)v * kMaxGrid + g];
-        acc = wave_sum(acc);
+        DD acc{0.0, 0.0};
+        for (unsigned g = lane; g < G; g += 64) {
+            const size_t o = (size_t)v * kMaxGrid + g;
+            acc = dd_add(acc, DD{part[o], part[o + lo_off]});
+        }
+        acc = wave_sum_dd(acc);
         if (lane == 0)
-            lrc[v] = acc;
+            lrc[v] = acc.hi + acc.lo;
     }
     __syncthreads();
 }
+
+// Visit the row pairs (i0, i0 + 1), i0 even, of the rows [lo, hi) (lo even)
+// with a wave-uniform loop: every lane of a wave takes part in each step
+// (the pair product exchanges x-neighbours across lanes).  A lane whose pair
+// starts at or past hi is inactive (act = false) but still computes with its
+// true pair while that lies inside the operator, so that its neighbours
+// across lanes are right; past n it computes the last pair.
+template <int NT, class F>
+__device__ __forceinline__ void for_pairs(int64_t lo, int64_t hi, int64_t n, F &&f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t pb = lo / 2 + wave * 64; 2 * pb < hi; pb += NT) {
+        const int64_t i0 = 2 * (pb + lane);
+        f(i0 < n ? i0 : n - 2, i0 < hi);
+    }
+}
+
+template <typename T>
+struct TypeTag {
+    using type = T;
+};
 
 // Workgroup-shared state of one solve.
 struct SolveShared {
     double Mk[kRMax][kPMax1][kPMax1];   // J_step^(k-1) / k!
     double Cj[kRMax][kPMax1][kPMax1];   // gam[i][b] * Mk[i][b][.]
-    double red[kNT / 64][2];
+    double red[kMaxNT / 64][2];
+    double res[2];                      // grid-wide maxima of the last exchange
     double lrc[kLrVals];                // low rank: W^T X of the coming product
     int ok;
 };
 
 // Algorithm 3 for one solve on a grid of G workgroups; this workgroup is
 // number bid of them and owns the rows of logical block lb.
-template <int KIND, int R, int RPT, bool EMEM, bool MIX>
+template <int KIND, int R, int RPT, bool EMEM, bool MIX, int NT = kNT>
 __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, const unsigned G,
                                            const unsigned bid, const int lb) {
     auto &Mk = sh.Mk;
@@ -242,12 +273,13 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     const int64_t n = P.n;
     int64_t lo, hi;
     if constexpr (EMEM) {
-        const int64_t chunk = (n + G - 1) / G;
+        // an even chunk: row pairs never straddle two workgroups
+        const int64_t chunk = ((n + G - 1) / G + 1) & ~(int64_t)1;
         lo = std::min<int64_t>(n, (int64_t)lb * chunk);
         hi = std::min<int64_t>(n, lo + chunk);
     } else {
-        lo = std::min<int64_t>(n, (int64_t)lb * kNT * RPT);
-        hi = std::min<int64_t>(n, lo + (int64_t)kNT * RPT);
+        lo = std::min<int64_t>(n, (int64_t)lb * NT * RPT);
+        hi = std::min<int64_t>(n, lo + (int64_t)NT * RPT);
     }
     const int tid = threadIdx.x;
     const int P1 = P.P1, p = P.p;
@@ -259,7 +291,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         else
             return Ereg[decltype(q)::value][c];
     };
-    int n32 = 0;   // terms evaluated in FP32
+    int n32 = 0, n32S = 0;   // recovery and S-series terms evaluated in FP32
     auto finish = [&](int st, int tS, int tR, int mS) {
         if (bid == 0 && tid == 0) {
             P.info[0] = st;
@@ -267,15 +299,23 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             P.info[2] = tR;
             P.info[3] = mS;
             P.info[4] = n32;
+            P.info[5] = n32S;
         }
     };
 
     // Operator rows: CSR rows of at most kCacheNnz entries stay in registers
     // for the whole solve; other kinds rebuild their row context per product.
     constexpr bool CACHED = (KIND == kCsrCached);
+    // stencils with E in memory and an even grid line: products by row pairs
+    // (the wide 16-wave kernel is launched for such operators only and has
+    // no single-row path)
+    constexpr bool PAIRS_ONLY = (NT == kWideNT);
+    bool pairs = PAIRS_ONLY;
+    if constexpr (KIND == kStencil && EMEM && !PAIRS_ONLY)
+        pairs = (A.nx % 2 == 0);
     CachedRow crow[CACHED ? RPT : 1];
     if constexpr (CACHED)
-        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+        for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
             load_cached_row(A, row, crow[decltype(q)::value]);
         });
     int lr_off = 0;   // low rank: column of W^T X holding the operand's first column
@@ -336,10 +376,12 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     // low rank: partial W^T X of a block this workgroup just wrote, for the
     // coming exchange (nlr values in all)
     int nlr = 0;
-    auto lr_part = [&]() { return P.lrpart + (size_t)(epoch & 1) * P.lrv * kMaxGrid; };
+    // [2 parities][hi, lo][lrv][kMaxGrid]
+    const size_t lr_lo = (size_t)P.lrv * kMaxGrid;
+    auto lr_part = [&]() { return P.lrpart + (size_t)(epoch & 1) * 2 * lr_lo; };
     auto publish = [&](const auto *X, int ncols, int voff) __attribute__((always_inline)) {
         if constexpr (KIND == kLowRank) {
-            lr_publish(A, n, lo, hi, X, ncols, voff, lr_part(), single ? 0u : bid);
+            lr_publish(A, n, lo, hi, X, ncols, voff, lr_part(), lr_lo, single ? 0u : bid);
             nlr = voff + ncols * A.rank;
         }
     };
@@ -348,19 +390,16 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         constexpr int NV = std::extent<std::remove_reference_t<decltype(v)>>::value;
         if (single) {
             wait_own_stores();
-            workgroup_max<NV, kNT>(v, red);
+            workgroup_max<NV, NT>(v, red);
             if constexpr (KIND == kLowRank)
-                lr_gather(lr_part(), 1, nlr, sh.lrc);
+                lr_gather(lr_part(), lr_lo, 1, nlr, sh.lrc);
             ++epoch;
             return true;
         }
-        double *pt = P.part + (size_t)(epoch & 1) * 2 * kMaxGrid;
-        store_partials<NV, kNT>(v, pt, red, bid);
-        if (!grid_sync(gs, &sh.ok))
+        if (!grid_max<NV, NT>(gs, &sh.ok, v, red, sh.res))
             return false;
-        load_partials<NV, kNT>(pt, G, v, red);
         if constexpr (KIND == kLowRank)
-            lr_gather(lr_part(), G, nlr, sh.lrc);
+            lr_gather(lr_part(), lr_lo, G, nlr, sh.lrc);
         ++epoch;
         return true;
     };
@@ -371,7 +410,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         Mk[i][b][c] = (b == c) ? 1.0 : 0.0;
     }
     double nrm[2] = {0.0, 0.0};
-    for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto) {
+    for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto) {
         double su = 0.0;
         for (int b = 0; b < P1; ++b) {
             const int pb = (b == 0) ? 0 : p + 1 - b;
@@ -395,18 +434,31 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         return;
     }
     double c2 = nrm[0], nS = nrm[1];
+    const double nS0 = nS;   // block norm of the first term (the series' start)
+    // a non-finite entry of V (t and the weights are checked on the host)
+    if (!(c2 <= 1.79769313486231570e308)) {
+        finish(PHICOMB_EINVAL, 0, 0, 0);
+        return;
+    }
 
     // ---- S-series (rec.D) with the stopping test (stopTm) after every term
     int status = PHICOMB_OK;
     int k = 1;
     double c1 = INFINITY;
     int par = 0;   // the latest term lives in U0 (par = 0) or U1
+    bool inS32 = false;   // the latest term is in Uf0/Uf1
     while (c1 + c2 > P.tol * nS) {
         if (k >= P.kcap) {
             status = PHICOMB_ENOCONV;
             break;
         }
         k = k + 1;
+        // mixed precision: the same FP64-head / FP32-tail rule as in the
+        // recovery steps, referenced to the smaller of the partial sum and
+        // the first term
+        const double nrefS = fmin(nS, nS0);
+        const bool s32 = MIX && (inS32 || (k >= 3 && c2 * kMixSafety <= P.mix_tau * nrefS &&
+                                           nrefS >= P.mix_lo && nS <= P.mix_hi));
         c1 = c2;
         const double rk = 1.0 / (double)k;
         // M_k = M_{k-1} J_step / k with J_step = a_i I + nu J  (J: ones on
@@ -430,43 +482,141 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         }
         const double *Uo = par ? P.U1 : P.U0;
         double *Un = par ? P.U0 : P.U1;
+        const float *Uo32 = par ? P.Uf1 : P.Uf0;
+        float *Un32 = par ? P.Uf0 : P.Uf1;
         double mx[2] = {0.0, 0.0};
         dense_pass(Uo, P.cS, P.xi);
-        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
-            double vr[kPMax1];   // reordered v: vr[b] = v_perm(b)(row)
+        // one pass of the term, with the operand of type TX and the new term
+        // stored as TS (mixed precision: FP32 tail); the precision is uniform
+        // over the grid, so the branch stays outside the row loops
+        auto s_pass = [&](auto tx, auto ts_) __attribute__((always_inline)) {
+            using TX = typename decltype(tx)::type;
+            using TS = typename decltype(ts_)::type;
+            const TX *Uo_;
+            TS *Un_;
+            if constexpr (std::is_same<TX, float>::value)
+                Uo_ = Uo32;
+            else
+                Uo_ = Uo;
+            if constexpr (std::is_same<TS, float>::value)
+                Un_ = Un32;
+            else
+                Un_ = Un;
+            // the J-coupling of block b for abscissa i from the reordered v
+            auto jterm = [&](int i, int b, const double *vr) -> double {
+                if (b == 0)
+                    return Cj[i][0][0] * vr[0];   // block 0 couples to itself only
+                double jt = 0.0;
 #pragma unroll
-            for (int b = 0; b < kPMax1; ++b)
-                vr[b] = (b < P1) ? P.V[row * P1 + ((b == 0) ? 0 : p + 1 - b)] : 0.0;
-            double su = 0.0, ss = 0.0;
+                for (int bb = 1; bb < kPMax1; ++bb)
+                    if (bb <= b)
+                        jt += Cj[i][bb][b] * vr[bb];
+                return jt;
+            };
+            if (pairs) {
+                // columns two at a time (a runtime loop keeps the registers of
+                // one chunk live, so that the wide 16-wave kernel fits)
+                for_pairs<NT>(lo, hi, n, [&](int64_t i0, bool act) {
+                    const PairCtx pc = pair_ctx(A, i0);
+                    double su0 = 0.0, ss0 = 0.0, su1 = 0.0, ss1 = 0.0;
 #pragma unroll 1
-            for (int b = 0; b < P1; ++b) {
-                double y[R];
-                opr(row, q, Uo, b * R, P.xi, y);
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    double jt;
-                    if (b == 0) {
-                        jt = Cj[i][0][0] * vr[0];   // block 0 couples to itself only
-                    } else {
-                        jt = 0.0;
-#pragma unroll
-                        for (int bb = 1; bb < kPMax1; ++bb)
-                            if (bb <= b)
-                                jt += Cj[i][bb][b] * vr[bb];
+                    for (int c0 = 0; c0 < P.cS; c0 += 2) {
+                        const int nc = (P.cS - c0 >= 2) ? 2 : 1;
+                        TX y0[2], y1[2];
+                        if (nc == 2) {
+                            apply_pair<2, TX, TX>(A, pc, Uo_, n, c0, P.xi, y0, y1);
+                        } else {
+                            TX z0[1], z1[1];
+                            apply_pair<1, TX, TX>(A, pc, Uo_, n, c0, P.xi, z0, z1);
+                            y0[0] = z0[0];
+                            y1[0] = z1[0];
+                            y0[1] = y1[1] = (TX)0;
+                        }
+                        if (!act)
+                            continue;
+                        for (int cc = 0; cc < nc; ++cc) {
+                            const int c = c0 + cc, b = c / R, i = c % R;
+                            const int pb = (b == 0) ? 0 : p + 1 - b;
+                            // J-coupling from the reordered v of both rows
+                            double j0 = 0.0, j1 = 0.0;
+                            if (b == 0) {
+                                j0 = Cj[i][0][0] * P.V[i0 * P1];
+                                j1 = Cj[i][0][0] * P.V[(i0 + 1) * P1];
+                            } else {
+                                for (int bb = 1; bb <= b; ++bb) {
+                                    const int pbb = p + 1 - bb;
+                                    j0 += Cj[i][bb][b] * P.V[i0 * P1 + pbb];
+                                    j1 += Cj[i][bb][b] * P.V[(i0 + 1) * P1 + pbb];
+                                }
+                            }
+                            (void)pb;
+                            double u0 = ((double)y0[cc] * P.ts[i]) * rk + j0;
+                            double u1 = ((double)y1[cc] * P.ts[i]) * rk + j1;
+                            const int64_t o = (int64_t)c * n + i0;
+                            typename Vec2<TS>::type uv = {(TS)u0, (TS)u1};
+                            *(typename Vec2<TS>::type *)(Un_ + o) = uv;
+                            u0 = (double)uv.x;
+                            u1 = (double)uv.y;
+                            auto sv = ld_pair(P.S + (int64_t)c * n, (unsigned)i0);
+                            sv.x += u0;
+                            sv.y += u1;
+                            *(typename Vec2<double>::type *)(P.S + o) = sv;
+                            su0 += fabs(u0);
+                            su1 += fabs(u1);
+                            ss0 += fabs(sv.x);
+                            ss1 += fabs(sv.y);
+                        }
                     }
-                    const double u = (y[i] * P.ts[i]) * rk + jt;
-                    const int64_t o = (int64_t)(b * R + i) * n + row;
-                    Un[o] = u;
-                    const double s = P.S[o] + u;
-                    P.S[o] = s;
-                    su += fabs(u);
-                    ss += fabs(s);
-                }
+                    if (act) {
+                        mx[0] = nmax(mx[0], nmax(su0, su1));
+                        mx[1] = nmax(mx[1], nmax(ss0, ss1));
+                    }
+                });
+                return;
             }
-            mx[0] = nmax(mx[0], su);
-            mx[1] = nmax(mx[1], ss);
-        });
-        publish(Un, P.cS, 0);
+            if constexpr (!PAIRS_ONLY) {
+            for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
+                double vr[kPMax1];   // reordered v: vr[b] = v_perm(b)(row)
+#pragma unroll
+                for (int b = 0; b < kPMax1; ++b)
+                    vr[b] = (b < P1) ? P.V[row * P1 + ((b == 0) ? 0 : p + 1 - b)] : 0.0;
+                double su = 0.0, ss = 0.0;
+#pragma unroll 1
+                for (int b = 0; b < P1; ++b) {
+                    TX y[R];
+                    opr(row, q, Uo_, b * R, P.xi, y);
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        double u = ((double)y[i] * P.ts[i]) * rk + jterm(i, b, vr);
+                        const int64_t o = (int64_t)(b * R + i) * n + row;
+                        const TS us = (TS)u;
+                        Un_[o] = us;
+                        u = (double)us;
+                        const double sn = P.S[o] + u;
+                        P.S[o] = sn;
+                        su += fabs(u);
+                        ss += fabs(sn);
+                    }
+                }
+                mx[0] = nmax(mx[0], su);
+                mx[1] = nmax(mx[1], ss);
+            });
+            }
+        };
+        if constexpr (MIX) {
+            if (inS32)
+                s_pass(TypeTag<float>{}, TypeTag<float>{});
+            else if (s32)
+                s_pass(TypeTag<double>{}, TypeTag<float>{});
+            else
+                s_pass(TypeTag<double>{}, TypeTag<double>{});
+        } else {
+            s_pass(TypeTag<double>{}, TypeTag<double>{});
+        }
+        if (MIX && s32)
+            publish(Un32, P.cS, 0);
+        else
+            publish(Un, P.cS, 0);
         publish(P.S, R, P.cS * A.rank);
         if (!exchange(mx)) {
             finish(PHICOMB_EDEVICE, k, 0, 0);
@@ -475,6 +625,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         c2 = mx[0];
         nS = mx[1];
         par ^= 1;
+        inS32 = s32;
+        n32S += s32 ? 1 : 0;
     }
     if (!(c2 == c2) || !(nS == nS))
         status = PHICOMB_EDEVICE;
@@ -491,7 +643,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         double mx[1] = {0.0};
         dense_pass(P.S, R, 0.0);
         lr_off = P.cS;
-        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+        for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
             double y[R];
             opr(row, q, P.S, 0, 0.0, y);
             const double v0 = P.V[row * P1];
@@ -552,7 +704,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             kk = kk + 1;
             const double nref = fmin(nE, nF0);
             const bool t32 =
-                MIX && (in32 || (j >= 2 && kk >= 2 && d2 * kMixSafety <= P.mix_tau * nref &&
+                MIX && (in32 || (kk >= 2 && d2 * kMixSafety <= P.mix_tau * nref &&
                                  nref >= P.mix_lo && nE <= P.mix_hi));
             d1 = d2;
             const double rk = 1.0 / (double)kk;
@@ -562,43 +714,92 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             float *Fn32 = par ? P.Uf0 : P.Uf1;
             double mx[2] = {0.0, 0.0};
             dense_pass(Fo, 2 * R, P.xi);
-            for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
-                double f[2 * R];
-                if (MIX && in32) {
-                    float yf[2 * R];
-                    opr(row, q, Fo32, 0, P.xi, yf);
+            // one Taylor term with the operand of type TX and the new term
+            // stored as TS; FP32 operands are multiplied in FP32
+            auto r_pass = [&](auto tx, auto ts_) __attribute__((always_inline)) {
+                using TX = typename decltype(tx)::type;
+                using TS = typename decltype(ts_)::type;
+                const TX *Fo_;
+                TS *Fn_;
+                if constexpr (std::is_same<TX, float>::value)
+                    Fo_ = Fo32;
+                else
+                    Fo_ = Fo;
+                if constexpr (std::is_same<TS, float>::value)
+                    Fn_ = Fn32;
+                else
+                    Fn_ = Fn;
+                // the new term's entry from the product y of the operand
+                auto term = [&](TX y, int c) -> double {
+                    if constexpr (std::is_same<TX, float>::value)
+                        return (double)((y * (float)P.ts[c % R]) * (float)rk);
+                    else
+                        return (double)(TS)(((double)y * P.ts[c % R]) * rk);
+                };
+                if (pairs) {
+                    // columns two at a time (2r is even), as in the S-series
+                    for_pairs<NT>(lo, hi, n, [&](int64_t i0, bool act) {
+                        const PairCtx pc = pair_ctx(A, i0);
+                        double sf0 = 0.0, sf1 = 0.0, se0 = 0.0, se1 = 0.0;
+#pragma unroll 1
+                        for (int c0 = 0; c0 < 2 * R; c0 += 2) {
+                            TX y0[2], y1[2];
+                            apply_pair<2, TX, TX>(A, pc, Fo_, n, c0, P.xi, y0, y1);
+                            if (!act)
+                                continue;
 #pragma unroll
-                    for (int c = 0; c < 2 * R; ++c) {
-                        const float ff = (yf[c] * (float)P.ts[c % R]) * (float)rk;
-                        Fn32[(int64_t)c * n + row] = ff;
-                        f[c] = (double)ff;
-                    }
-                } else {
-                    double y[2 * R];
-                    opr(row, q, Fo, 0, P.xi, y);
-#pragma unroll
-                    for (int c = 0; c < 2 * R; ++c) {
-                        f[c] = (y[c] * P.ts[c % R]) * rk;
-                        if (MIX && t32) {
-                            const float ff = (float)f[c];
-                            Fn32[(int64_t)c * n + row] = ff;
-                            f[c] = (double)ff;
-                        } else {
-                            Fn[(int64_t)c * n + row] = f[c];
+                            for (int cc = 0; cc < 2; ++cc) {
+                                const int c = c0 + cc;
+                                const double f0 = term(y0[cc], c), f1 = term(y1[cc], c);
+                                const int64_t o = (int64_t)c * n + i0;
+                                typename Vec2<TS>::type fv = {(TS)f0, (TS)f1};
+                                *(typename Vec2<TS>::type *)(Fn_ + o) = fv;
+                                auto ev = ld_pair(P.E + (int64_t)c * n, (unsigned)i0);
+                                ev.x += f0;
+                                ev.y += f1;
+                                *(typename Vec2<double>::type *)(P.E + o) = ev;
+                                sf0 += fabs(f0);
+                                sf1 += fabs(f1);
+                                se0 += fabs(ev.x);
+                                se1 += fabs(ev.y);
+                            }
                         }
-                    }
+                        if (act) {
+                            mx[0] = nmax(mx[0], nmax(sf0, sf1));
+                            mx[1] = nmax(mx[1], nmax(se0, se1));
+                        }
+                    });
+                    return;
                 }
-                double sf = 0.0, se = 0.0;
+                if constexpr (!PAIRS_ONLY) {
+                for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
+                    TX y[2 * R];
+                    opr(row, q, Fo_, 0, P.xi, y);
+                    double sf = 0.0, se = 0.0;
 #pragma unroll
-                for (int c = 0; c < 2 * R; ++c) {
-                    double &e = Eref(row, q, c);
-                    e = e + f[c];
-                    sf += fabs(f[c]);
-                    se += fabs(e);
+                    for (int c = 0; c < 2 * R; ++c) {
+                        const double f = term(y[c], c);
+                        Fn_[(int64_t)c * n + row] = (TS)f;
+                        double &e = Eref(row, q, c);
+                        e = e + f;
+                        sf += fabs(f);
+                        se += fabs(e);
+                    }
+                    mx[0] = nmax(mx[0], sf);
+                    mx[1] = nmax(mx[1], se);
+                });
                 }
-                mx[0] = nmax(mx[0], sf);
-                mx[1] = nmax(mx[1], se);
-            });
+            };
+            if constexpr (MIX) {
+                if (in32)
+                    r_pass(TypeTag<float>{}, TypeTag<float>{});
+                else if (t32)
+                    r_pass(TypeTag<double>{}, TypeTag<float>{});
+                else
+                    r_pass(TypeTag<double>{}, TypeTag<double>{});
+            } else {
+                r_pass(TypeTag<double>{}, TypeTag<double>{});
+            }
             if (MIX && t32)
                 publish(Fn32, 2 * R, 0);
             else
@@ -630,7 +831,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         const bool last = (j == P.s_int - 1);
         double *Fx = par ? P.U1 : P.U0;   // overwrite the latest term: only E is needed
         double mx[1] = {0.0};
-        for_rows<RPT, EMEM>(lo, hi, [&](int64_t row, auto q) {
+        for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
             double f1[R], f2[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
@@ -674,11 +875,11 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
 }
 
 // ------------------------------------------------------------ single solve
-template <int KIND, int R, int RPT, bool EMEM, bool MIX>
-__global__ __launch_bounds__(kNT) void solve_kernel(SolveArgs P) {
+template <int KIND, int R, int RPT, bool EMEM, bool MIX, int NT = kNT>
+__global__ __launch_bounds__(NT) void solve_kernel(SolveArgs P) {
     __shared__ SolveShared sh;
-    solve_body<KIND, R, RPT, EMEM, MIX>(P, sh, gridDim.x, blockIdx.x,
-                                        xcd_logical_block(blockIdx.x, gridDim.x));
+    solve_body<KIND, R, RPT, EMEM, MIX, NT>(P, sh, gridDim.x, blockIdx.x,
+                                            xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 using KernelFn = void (*)(SolveArgs);
@@ -716,8 +917,16 @@ KernelFn pick_r(int r, int rpt, bool emem, bool mix) {
     }
 }
 
-// Low-rank variants (instantiated in solve_lowrank.hip).
+// Variants per operator kind, each instantiated in a translation unit of its
+// own so that they compile in parallel (solve_<kind>.hip).
 KernelFn pick_lowrank(int r, int rpt, bool emem, bool mix);
+KernelFn pick_stencil(int r, int rpt, bool emem, bool mix);
+// E in memory, 1024 threads (16 waves) per workgroup, row pairs only: stencil
+// operators with an even grid line and r <= 2 (nullptr otherwise)
+KernelFn pick_stencil_wide(int r, bool mix);
+KernelFn pick_csr(int r, int rpt, bool emem, bool mix);
+KernelFn pick_csr_cached(int r, int rpt, bool mix);   // E in registers only
+KernelFn pick_dense(int r);                            // E in memory, FP64
 
 // ---------------------------------------------------------------- host side
 // (implemented in solve.hip)

@@ -67,3 +67,23 @@ def test_apply_rejects_low_rank_and_bad_shapes():
         pc.phicomb_op_apply(op.h, X, 0.0, torch.zeros_like(X))
     assert e.value.status == pc.EINVAL
     op.close()
+
+
+@pytest.mark.parametrize("grid,dim,sd", [
+    ((2, 3, 5), 3, 0.0),       # two-point grid lines: every pair is a whole line
+    ((6, 5, 4), 3, 100.0),     # superdiagonal across grid-line ends
+    ((30, 17, 1), 2, 0.0),     # 255 pairs: a partial last wave
+    ((64, 64, 1), 2, -7.0),
+    ((130, 3, 2), 3, 1.0),     # a grid line longer than a wave of pairs
+])
+@pytest.mark.parametrize("ncols", [1, 5, 16])
+def test_apply_stencil_row_pairs(grid, dim, sd, ncols):
+    """Stencils with an even grid line take the row-pair kernel (x-neighbours
+    across lanes, first and last lane of a wave loading their own); random
+    non-symmetric coefficients so that every neighbour's weight is seen."""
+    rng = np.random.default_rng(sum(grid) + ncols)
+    coef = rng.uniform(-2, 2, 7)
+    if dim == 2:
+        coef[5:] = 0.0
+    st = wl.Stencil(dim, grid, coef, sd)
+    _check(st, ncols, 0.75, seed=ncols)

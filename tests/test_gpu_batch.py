@@ -162,3 +162,43 @@ def test_batch_rejects_mixed_kinds():
     assert e.value.status == pc.EINVAL
     for o in ops:
         o.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config4_full_batch_against_closed_form(precision):
+    """The whole benchmark batch (256 kappa-Laplacians, side U{32..256},
+    kappa logU[1e-2, 1e2], p, r U{1,2,3}, t logU[1e-5, 1e-2], tol 1e-8,
+    s_int up to ~16 000), one launch with the GPU's own parameters: every
+    instance against the DST-I eigen-decomposition closed form, within
+    max(10 tol, 1e-12) relative 2-norm per column in FP64 and 10 tol in
+    mixed precision."""
+    import torch
+    prec = pc.FP64 if precision == "fp64" else pc.MIXED
+    probs = wl.config4()
+    ops = [pc.Operator(pr.op) for pr in probs]
+    prms = [o.params(pr.tol, v=pr.v) for o, pr in zip(ops, probs)]
+    Vd = [torch.from_numpy(pr.V).cuda() for pr in probs]
+    Wd = [torch.full((pr.n, pr.r), np.nan, dtype=torch.float64, device="cuda") for pr in probs]
+    items = [(ops[k].h, prms[k], pr.p, pr.r, pr.t, pr.beta, Vd[k], Wd[k], pr.tol)
+             for k, pr in enumerate(probs)]
+    torch.cuda.synchronize()
+    b = pc.phicomb_batch_create(items, prec)
+    say(f"[gpu-batch] config 4, {precision}: {len(probs)} instances, one launch")
+    st, stats = pc.phicomb_batch_run(b, len(probs))
+    torch.cuda.synchronize()
+    assert st == pc.OK, pc.phicomb_strerror(st)
+    bar = 10 * probs[0].tol if prec == pc.MIXED else max(10 * probs[0].tol, 1e-12)
+    worst, wk = 0.0, -1
+    for k, pr in enumerate(probs):
+        assert stats[k].status == pc.OK, k
+        ref = refs.dst_laplacian(pr.op, pr.t, pr.beta, pr.V)
+        err = refs.rel2_cols(Wd[k].cpu().numpy(), ref).max()
+        if err > worst:
+            worst, wk = err, k
+        assert err <= bar, (k, pr.n, pr.p, pr.r, stats[k].s_int, err)
+    say(f"      {stats[0].ms:.0f} ms, s_int up to {max(s.s_int for s in stats)}, "
+        f"fp32 terms {sum(s.fp32_terms for s in stats)}; worst error vs closed form "
+        f"{worst:.2e} (instance {wk}, n={probs[wk].n})")
+    pc.phicomb_batch_destroy(b)
+    for o in ops:
+        o.close()

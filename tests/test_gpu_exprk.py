@@ -118,47 +118,57 @@ def test_exprk4s6_rejects_bad_arguments():
     lr.close()
 
 
-@pytest.mark.parametrize("kind", ["stencil", "dense"])
+@pytest.mark.parametrize("kind", ["stencil", "dense", "dense2048"])
 def test_exprk4s6_other_operator_kinds(kind):
     """The right-hand side through the stencil row product (a 2-D Laplacian
     stencil) and through a dense operator's CSR form, against the oracle's
-    integrator with pinned parameters."""
+    integrator with pinned parameters.  The n = 2048 dense operator (the
+    served stream's largest, upper triangular non-normal) needs more solve
+    workgroups (one per 32 rows) than its row count alone asks for."""
+    steps = 20
     if kind == "stencil":
         op = wl.laplacian_2d(40, kappa=1e-3)
         u0 = wl.adr_initial(40)
-    else:
+    elif kind == "dense":
         rng = np.random.default_rng(5)
         A = rng.standard_normal((300, 300)) * 0.2 - np.diag(rng.uniform(0, 30, 300))
         op = wl.Dense(np.ascontiguousarray(A))
         u0 = rng.uniform(0, 1, 300)
+    else:
+        rng = np.random.default_rng(6)
+        op = wl.dense_upper_nonnormal(2048, rng)
+        u0 = rng.uniform(0, 1, 2048)
+        steps = 3
     gc = wl.adr_reaction(50.0)
     h = 1e-3
     po = oracle.params(op, TOL, wl.params_vector(op.n))
-    say(f"[gpu] expRK4s6 {kind} n={op.n} 20 steps pinned")
-    uo, calls = oracle.exprk4s6(op, gc, u0, h, 20, TOL, po["shift"], po["s"])
+    say(f"[gpu] expRK4s6 {kind} n={op.n} {steps} steps pinned")
+    uo, calls = oracle.exprk4s6(op, gc, u0, h, steps, TOL, po["shift"], po["s"])
     H = pc.Operator(op)
-    ug, st = _run_gpu(H, pc.params_from_dict(po), gc, u0, h, 20)
+    ug, st = _run_gpu(H, pc.params_from_dict(po), gc, u0, h, steps)
     H.close()
     err = np.abs(ug - uo).max() / np.abs(uo).max()
     say(f"      err {err:.2e} terms {st['terms']}")
-    assert st["status"] == pc.OK and st["calls"] == 80
+    assert st["status"] == pc.OK and st["calls"] == 4 * steps
     assert err <= 1e-10, err
 
 
-def test_exprk4s6_failing_call_leaves_last_completed_step(monkeypatch):
-    """A term cap of 2 (forced from the host) makes the first call of the
-    first step stop with ENOCONV; the status comes back and u keeps its
-    initial value (every step's update is skipped once a call has failed)."""
+def test_exprk4s6_failing_call_leaves_last_completed_step():
+    """A tolerance no Taylor sum can meet makes the first call of the first
+    step stop with ENOCONV: with a unit step the scaled steps have norm
+    about 17 (the parameters are chosen for tol 1e-7), whose Taylor terms
+    are still ~1e-77 of the sum at the 150-term cap, far above 1e-300 (a
+    small step's terms would underflow to zero first and end the loop).
+    The status comes back and u keeps its initial value (every step's
+    update is skipped once a call has failed)."""
     import torch
     op, gc, u0 = _setup()
     h, _ = wl.adr_steps(1)
     H = pc.Operator(op)
     prm = H.params(TOL, v=wl.params_vector(op.n))
     u = torch.from_numpy(u0.copy()).cuda()
-    monkeypatch.setenv("PHICOMB_TERM_CAP", "2")
     with pytest.raises(pc.PhicombError) as e:
-        pc.phicomb_exprk4s6(H.h, prm, gc, h, 3, TOL, pc.FP64, u)
-    monkeypatch.delenv("PHICOMB_TERM_CAP")
+        pc.phicomb_exprk4s6(H.h, prm, gc, 1.0, 3, 1e-300, pc.FP64, u)
     torch.cuda.synchronize()
     assert e.value.status == pc.ENOCONV
     assert np.array_equal(u.cpu().numpy(), u0)

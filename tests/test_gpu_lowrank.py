@@ -2,18 +2,20 @@
 through the C ABI, against the CPU oracle and the closed form of the
 low-rank linear combination.
 
-Parity with the parameters pinned to the oracle's: relative 2-norm 1e-12
-per column, or, where the method's own rounding is larger (the hump of a
-Taylor step of a strongly non-normal core), ten times the oracle's own
+Both sides form the n-term inner products W^T x compensated (exact products
+and sums carried as double-double pairs, rounded once), so the order in
+which they are summed no longer matters.  Parity with the parameters pinned
+to the oracle's: relative 2-norm 1e-12 per column, or, where the method's
+own rounding is larger (the strongly non-normal M3 core amplifies the
+rounding of the row products and Taylor sums), ten times the oracle's own
 relative error against the closed form; the GPU result must then also be
-that close to the closed form itself.  The two sides sum the n-term inner
-products W^T x in different orders, so their rounding errors are
-independent realisations of the same size, which the hump amplifies by
-different amounts (up to 5x apart on the M2 core).  End to end (each side's own parameters):
-within the paper's Tables 2-4 accuracy (factor 10, floor 100 u), with a
-hundredfold allowance in the cases where Algorithm 1 as printed leaves a
-rounding hump.
+that close to the closed form itself.  End to end (the GPU's own
+parameters), at the paper's n and p, for every row of Tables 2-4: within
+the paper's accuracy (factor 10, floor 100 u).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -28,12 +30,17 @@ pytestmark = pytest.mark.gpu
 
 TOL_FP64 = 1e-12
 U53 = 2.0 ** -53
-HUMP = {("M1", 1.0), ("M2", 10.0)}
-TABLE = {  # phimv column of Tables 2-4 (relative 1-norm errors)
-    "M1": dict(zip([0.1, 1.0, 10.0], [1.65e-16, 5.52e-15, 7.99e-13])),
-    "M2": dict(zip([0.1, 1.0, 10.0], [9.38e-12, 1.46e-09, 3.78e-10])),
-    "M3": dict(zip([1e-5, 1e-3], [2.39e-10, 1.91e-09])),
-}
+# phimv column of Tables 2-4 (relative 1-norm errors), stored with its citation
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "tables2to4_phimv.json")) as _f:
+    _G = json.load(_f)
+TABLE = {c: dict(zip([float(t) for t in _G[c]["t"]], _G[c]["rel_err_1norm"]))
+         for c in ("M1", "M2", "M3")}
+ROWS = [(c, t) for c in ("M1", "M2", "M3") for t in TABLE[c]]
+# rows whose oracle solve at the paper's n takes more than a few seconds on
+# one core (s_int from 5 to 73): pinned parity runs at n = 20 000 for them
+LONG = {("M1", 50.0), ("M1", 100.0), ("M2", 50.0), ("M2", 100.0),
+        ("M3", 1.0), ("M3", 10.0)}
 
 
 def _exact(pr):
@@ -93,6 +100,13 @@ def test_lowrank_params_match_oracle(core):
     ("M3", 1e-5, 4000),
     ("M3", 1e-3, 4000),
     ("M1", 10.0, 100003),     # many workgroups, ragged last one
+    ("M1", 50.0, 20000),
+    ("M1", 100.0, 20000),
+    ("M2", 50.0, 20000),
+    ("M2", 100.0, 20000),
+    ("M3", 0.1, 20000),
+    ("M3", 1.0, 20000),
+    ("M3", 10.0, 20000),
 ])
 def test_lowrank_pinned(core, t, n):
     _pinned(wl.exp3_problem(core, t, n=n, seed=1), f"t={t}")
@@ -116,22 +130,30 @@ def test_lowrank_p0_is_exponential_action():
     _pinned(pr, "p=0")
 
 
-@pytest.mark.parametrize("core,t", [
-    ("M1", 0.1), ("M1", 1.0), ("M1", 10.0),
-    ("M2", 0.1), ("M2", 1.0), ("M2", 10.0),
-    ("M3", 1e-5), ("M3", 1e-3),
-])
+@pytest.mark.parametrize("core,t", ROWS)
 def test_lowrank_paper_sizes(core, t):
-    """The paper's n and p: pinned parity with the oracle over every entry,
-    and the end-to-end result (GPU parameters) against the closed form."""
+    """Every row of Tables 2-4 at the paper's n and p: the end-to-end result
+    (GPU parameters) against the closed form within 10x the paper's error;
+    pinned parity with the oracle over every entry where the oracle finishes
+    in seconds at that size (the other rows: at n = 20 000 above, and the
+    GPU with the oracle's parameters against the closed form here)."""
     pr = wl.exp3_problem(core, t, seed=0)
-    Wg, Wo, ex = _pinned(pr, f"t={t} (paper size)")
+    ex = _exact(pr)
+    bar = max(10 * TABLE[core][t], 100 * U53)
+    if (core, t) in LONG:
+        say(f"[gpu] lowrank {pr.name} n={pr.n} p={pr.p} (paper size, oracle parameters)")
+        prm = oracle.params(pr.op, pr.tol, pr.v)
+        Wg, sg, _ = gpu_solve(pr, prm=prm)
+        e_pin = refs.rel1_cols(Wg, ex)[0]
+        say(f"      s_int={sg['s_int']} rel1 err {e_pin:.2e}")
+        assert sg["status"] == pc.OK
+        assert e_pin <= bar, (e_pin, bar)
+    else:
+        _pinned(pr, f"t={t} (paper size)")
     Wg2, sg2, prm = gpu_solve(pr)
     err = refs.rel1_cols(Wg2, ex)[0]
-    bar = max(10 * TABLE[core][t], 100 * U53)
-    if (core, t) in HUMP:
-        bar *= 100
     say(f"      end to end: s_int={sg2['s_int']} rel1 err {err:.2e} (paper {TABLE[core][t]:.2e})")
+    assert sg2["status"] == pc.OK
     assert err <= bar, (err, bar)
 
 

@@ -98,3 +98,14 @@ def test_config3_nonnormal_full_size_mixed_sampled(tol):
     assert err.max() <= 10 * tol
     if tol >= 1e-6:
         assert sm["fp32_terms"] > 0
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_series_only_mixed_tail(kind):
+    """With s_int = 1 every term is in the S-series: its FP32 tail (the same
+    head/tail rule as the recovery steps) is used and the result stays within
+    10 tol of the FP64 oracle."""
+    pr = dataclasses.replace(wl.config2(nside=96, as_csr=(kind == "csr")), tol=1e-6)
+    sg, _ = _mixed_vs_oracle(pr, label=f"{kind} s_int=1")
+    assert sg["s_int"] == 1
+    assert sg["fp32_terms"] > 0

@@ -137,6 +137,23 @@ def test_config3_nonnormal_full_size_sampled(tol):
     assert np.allclose(cn, g["col_norm2"], rtol=TOL_FP64, atol=0)
 
 
+def test_large_nonsymmetric_stencil_row_pairs_pinned():
+    """Past 2^20 rows the partial sums E live in memory and stencil products
+    run by row pairs (x-neighbours across lanes).  A non-symmetric 3-D stencil
+    (every neighbour weight different, plus a superdiagonal) on a 104^3 grid
+    (n = 1 124 864: 256 workgroups of 4394 rows, pairs straddling waves and
+    a ragged last workgroup), p = 1, r = 2, against the oracle with pinned
+    parameters at the FP64 parity bar."""
+    rng = np.random.default_rng(31)
+    h2 = 105.0 ** 2
+    coef = np.array([-6.0, 1.3, 0.7, 1.1, 0.9, 1.2, 0.8]) * h2
+    st = wl.Stencil(3, (104, 104, 104), coef, 0.03 * h2)
+    V = np.ascontiguousarray(rng.standard_normal((st.n, 2)))
+    pr = wl.Problem("stencil3d_104_nonsym", st, 1, 2, np.array([2e-4, 5e-4]),
+                    rng.uniform(-1, 1, (2, 2)), V, 1e-12, wl.params_vector(st.n))
+    _compare(pr, label="E in memory, row pairs")
+
+
 # --------------------------------------------------------------- edge cases
 def test_p0_exponential_only():
     pr = wl.config2(nside=40)
@@ -221,38 +238,63 @@ def test_overflow_guard_and_invalid_inputs():
     with pytest.raises(pc.PhicombError) as e:
         op.solve(prm, pr.t, pr.beta, V, -1.0)
     assert e.value.status == pc.EINVAL
+    # a non-finite entry of V is found in the device's first pass over V
+    Vbad = V.clone()
+    Vbad[100, 2] = float("nan")
+    with pytest.raises(pc.PhicombError) as e:
+        op.solve(prm, pr.t, pr.beta, Vbad, pr.tol)
+    assert e.value.status == pc.EINVAL
+    Vbad[100, 2] = float("inf")
+    with pytest.raises(pc.PhicombError) as e:
+        op.solve(prm, pr.t, pr.beta, Vbad, pr.tol)
+    assert e.value.status == pc.EINVAL
+    # the operator still solves normally afterwards
+    W, st = op.solve(prm, pr.t, pr.beta, V, pr.tol)
+    assert st.status == pc.OK
     op.close()
 
 
 # ------------------------------------------- second experiment (Sec. 5, Table 1)
-def test_second_experiment_chebyshev():
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_second_experiment_chebyshev(k):
     """Dense, highly non-normal collocation Laplacian (n = 99), p = 6, one
-    solve per t = 1e-4 .. 1e-1 at tol 2^-53: end to end (parameters from
-    the GPU) within 10x the paper's Table 1 errors against an exact
-    reference, and parity with the oracle at pinned parameters."""
+    solve per t = 1e-4 .. 1e-1 at tol 2^-53.  Parity with the oracle at the
+    oracle's parameters and at the GPU's own parameters; end to end
+    (parameters from the GPU) within 10x the paper's Table 1 error against
+    an exact reference, or within 10x the error the oracle itself reaches
+    with the same parameters where that is larger (xi* and s are set by a
+    rounding-limited objective and the error of this non-normal matrix moves
+    with them)."""
     import json
     import os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_phimv.json")))
-    for pr, env in zip(wl.exp2_problems()[:4], g["rel_err_1norm"][:4]):
-        say(f"[gpu] {pr.name}")
-        Wq = refs.exact_dense_q(pr.op.A, pr.t, pr.beta, pr.V)
-        Wg, sg, prm = gpu_solve(pr)
-        e_end = refs.rel1_cols(Wg, Wq)[0]
-        po = oracle.params(pr.op, pr.tol, pr.v)
-        Wo, so = oracle.solve(pr.op, pr.p, pr.r, pr.t, pr.beta, pr.V, pr.tol, po["shift"], po["s"])
-        Wp, sp_, _ = gpu_solve(pr, prm=po)
-        e_par = refs.rel2_cols(Wp, Wo)[0]
-        # where the method's own rounding error exceeds 1e-12 (tens of
-        # thousands of scaling steps on a non-normal matrix; Table 1 reports
-        # 1.2e-12 at t = 0.1), two correct FP64 evaluations differ by up to
-        # that error: the bar is the oracle's own error against the exact one
-        e_orc = refs.rel2_cols(Wo, Wq)[0]
-        e_orc1 = refs.rel1_cols(Wo, Wq)[0]
-        say(f"      s_int={sg['s_int']} end-to-end rel1 err {e_end:.2e} (Table 1: {env:.1e}, "
-            f"oracle {e_orc1:.2e}); pinned vs oracle {e_par:.2e} (oracle vs exact {e_orc:.2e})")
-        # the parameters are rounding-dependent (the objective is limited by
-        # rounding at m = 61): the end-to-end bar follows the oracle's own
-        # end-to-end error where that exceeds the paper's
-        assert e_end <= 10 * max(env, e_orc1)
-        assert sp_["s_int"] == so["s_int"]
-        assert e_par <= max(TOL_FP64, e_orc)
+    pr, env = wl.exp2_problems()[k], g["rel_err_1norm"][k]
+    say(f"[gpu] {pr.name}")
+    Wq = refs.exact_dense_q(pr.op.A, pr.t, pr.beta, pr.V)
+    Wg, sg, prm = gpu_solve(pr)
+    e_end = refs.rel1_cols(Wg, Wq)[0]
+    po = oracle.params(pr.op, pr.tol, pr.v)
+    Wo, so = oracle.solve(pr.op, pr.p, pr.r, pr.t, pr.beta, pr.V, pr.tol, po["shift"], po["s"])
+    Wp, sp_, _ = gpu_solve(pr, prm=po)
+    e_par = refs.rel2_cols(Wp, Wo)[0]
+    # the oracle at the GPU's own parameters
+    Wog, sog = oracle.solve(pr.op, pr.p, pr.r, pr.t, pr.beta, pr.V, pr.tol, prm.shift, prm.s)
+    e_par_g = refs.rel2_cols(Wg, Wog)[0]
+    # where the method's own rounding error exceeds 1e-12 (tens of
+    # thousands of scaling steps on a non-normal matrix; Table 1 reports
+    # 1.2e-12 at t = 0.1), two correct FP64 evaluations differ by up to
+    # that error: the bar is the oracle's own error against the exact one
+    e_orc = refs.rel2_cols(Wo, Wq)[0]
+    e_orc1 = refs.rel1_cols(Wo, Wq)[0]
+    e_orc1_g = refs.rel1_cols(Wog, Wq)[0]
+    say(f"      params gpu: shift {prm.shift:.6e} s {prm.s:.6e} n_feval {prm.n_feval} "
+        f"s_int {sg['s_int']}; oracle: shift {po['shift']:.6e} s {po['s']:.6e} "
+        f"n_feval {po['n_feval']} s_int {so['s_int']}")
+    say(f"      end-to-end rel1 err {e_end:.2e} (Table 1: {env:.1e}); oracle at its own "
+        f"parameters {e_orc1:.2e}, at the GPU's {e_orc1_g:.2e}; pinned vs oracle "
+        f"{e_par:.2e} / {e_par_g:.2e} (oracle vs exact {e_orc:.2e})")
+    assert e_end <= 10 * max(env, e_orc1_g)
+    assert sp_["s_int"] == so["s_int"]
+    assert sog["s_int"] == sg["s_int"]
+    assert e_par <= max(TOL_FP64, e_orc)
+    assert e_par_g <= max(TOL_FP64, refs.rel2_cols(Wog, Wq)[0])

@@ -166,3 +166,74 @@ def test_served_mixed_precision():
         assert err <= 10 * pr.tol, err
         assert stats["fp32_terms"] > 0
     h.close()
+
+
+def test_served_stream_sample_at_config5_sizes():
+    """Five seconds of the served stream (Poisson arrivals at 200/s over the
+    resident pool of 64 stencils with n up to 2^20 and 32 dense non-normal
+    operators with n in 256..2048; p, r, tol and precision per request as in
+    the benchmark), submitted at their arrival times; a seeded 2 % sample is
+    checked: stencil requests against the DST-I closed form within
+    max(10 tol, 1e-12), dense requests against the oracle run with the same
+    (GPU) parameters at the parity bar (1e-12 FP64)."""
+    import torch
+    ops, reqs = wl.config5_stream(duration_s=5.0)
+    handles = [pc.Operator(o) for o in ops]
+    prms = {}
+    for i, h in enumerate(handles):
+        for tol in (1e-6, 1e-10):
+            prms[(i, tol)] = h.params(tol, v=wl.params_vector(ops[i].n))
+    pc.phicomb_serve_config(0, 8)
+    pick = np.random.default_rng(2024).uniform(size=len(reqs)) < 0.02
+    say(f"[gpu] served stream: {len(reqs)} requests over 5 s, {int(pick.sum())} sampled")
+    pending, sampled = [], []
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        assert now < 120.0, "served stream did not drain"
+        while i < len(reqs) and reqs[i]["arrival"] <= now:
+            q = reqs[i]
+            op = ops[q["op_index"]]
+            t, beta, V = wl.stream_request_inputs(op, q)
+            prec = pc.MIXED if (q["tol"] == 1e-6 and op.kind != "dense") else pc.FP64
+            Vd = torch.from_numpy(V).cuda()
+            Wd = torch.empty((op.n, q["r"]), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            tk = pc.phicomb_submit(handles[q["op_index"]].h, prms[(q["op_index"], q["tol"])],
+                                   q["p"], q["r"], t, beta, Vd, q["tol"], prec, Wd)
+            pending.append((tk, i, Vd, Wd, t, beta, V, prec))
+            i += 1
+        still = []
+        for item in pending:
+            st, _ = pc.phicomb_poll(item[0])
+            if st == pc.PENDING:
+                still.append(item)
+                continue
+            assert st == pc.OK, pc.phicomb_strerror(st)
+            if pick[item[1]]:
+                sampled.append((item[1], item[5], item[4], item[6], item[3].cpu().numpy(),
+                                item[7]))
+        pending = still
+        time.sleep(0.0003)
+    worst = {}
+    for k, beta, t, V, W, prec in sampled:
+        q = reqs[k]
+        op = ops[q["op_index"]]
+        if op.kind == "stencil":
+            ref = refs.dst_laplacian(op, t, beta, V)
+            bar = max(10 * q["tol"], 1e-12)
+        else:
+            pg = prms[(q["op_index"], q["tol"])]
+            ref, _ = oracle.solve(op, q["p"], q["r"], t, beta, V, q["tol"], pg.shift, pg.s)
+            bar = TOL_FP64 if prec == pc.FP64 else 10 * q["tol"]
+        err = refs.rel2_cols(W, ref).max()
+        key = f"{op.kind} n={op.n} tol={q['tol']:g}"
+        worst[key] = max(worst.get(key, 0.0), err)
+        assert err <= bar, (k, key, q["p"], q["r"], err, bar)
+    for key in sorted(worst):
+        say(f"      {key}: {worst[key]:.2e}")
+    assert any(ops[reqs[k]["op_index"]].kind == "dense" for k, *_ in sampled)
+    assert max(ops[reqs[k]["op_index"]].n for k, *_ in sampled) > 100000
+    for h in handles:
+        h.close()
