@@ -173,6 +173,28 @@ int phicomb_solve(phicomb_op op, const phicomb_params_t *prm, int p, int r,
                   const double *t, const double *beta, const void *V, double tol,
                   int precision, void *W, void *stream, phicomb_stats_t *stats);
 
+/* --------------------------------------------------- solve without allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as phicomb_solve (same kernels, same results), with the work blocks
+ * in a static device array of PHICOMB_STATIC_BYTES per device instead of
+ * the operator's grow-only workspace.  The call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine (the array's address and
+ * two timing events are set up once per device, at the first call).  The
+ * caller still passes V and W.  EINVAL when the work blocks of this shape
+ * (phicomb_request_bytes minus V and W, i.e. about 8 n ((p+1) r + 2 max((p+1)
+ * r, 2r) + 2r) bytes, plus the FP32 blocks of mixed precision) exceed the
+ * array, or when the operator was created on another device than the
+ * current one; otherwise as phicomb_solve.  Every call on a device shares
+ * that device's array, which keeps the last call's contents; calls that
+ * would overlap on one device are serialised by the library (each waits for
+ * the previous one to finish). */
+#define PHICOMB_STATIC_BYTES (64ll << 20)
+
+int phicomb_solve_static(phicomb_op op, const phicomb_params_t *prm, int p, int r,
+                         const double *t, const double *beta, const void *V, double tol,
+                         int precision, void *W, void *stream, phicomb_stats_t *stats);
+
 /* ---------------------------------------------------------------- serving
  * Asynchronous form of phicomb_solve for a request stream (continuous
  * batching; the paper computes the parameters once per operator and reuses

@@ -89,6 +89,7 @@ def _lib():
             "phicomb_op_n": ([P], I64),
             "phicomb_params": ([P, D, I32, P, C.c_uint64, P, P], I32),
             "phicomb_solve": ([P, P, I32, I32, P, P, P, D, I32, P, P, P], I32),
+            "phicomb_solve_static": ([P, P, I32, I32, P, P, P, D, I32, P, P, P], I32),
             "phicomb_submit": ([P, P, I32, I32, P, P, P, D, I32, P, P], I32),
             "phicomb_poll": ([P, P], I32),
             "phicomb_serve_config": ([I64, I32], I32),
@@ -205,6 +206,26 @@ def phicomb_solve(h, prm: ParamsT, p: int, r: int, t, beta, V, tol: float, preci
                               C.c_void_p(W.data_ptr()), _stream_ptr(stream), C.byref(stats))
     _check(st, "phicomb_solve")
     return stats
+
+
+def phicomb_solve_static(h, prm: ParamsT, p: int, r: int, t, beta, V, tol: float,
+                         precision: int, W, stream=None) -> StatsT:
+    """phicomb_solve with the work blocks in the library's static device
+    array (no allocation in the call); same arguments."""
+    ta = np.ascontiguousarray(t, dtype=np.float64)
+    ba = np.ascontiguousarray(beta, dtype=np.float64)
+    _check_device_tensor(V, (None, p + 1), "V")
+    _check_device_tensor(W, (None, r), "W")
+    stats = StatsT()
+    st = _lib().phicomb_solve_static(h, C.byref(prm), int(p), int(r), _np_ptr(ta), _np_ptr(ba),
+                                     C.c_void_p(V.data_ptr()), float(tol), int(precision),
+                                     C.c_void_p(W.data_ptr()), _stream_ptr(stream),
+                                     C.byref(stats))
+    _check(st, "phicomb_solve_static")
+    return stats
+
+
+STATIC_BYTES = 64 << 20   # PHICOMB_STATIC_BYTES
 
 
 def phicomb_op_apply(h, X, shift: float, Y, stream=None, timed: bool = False) -> float:

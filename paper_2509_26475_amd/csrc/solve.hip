@@ -386,4 +386,66 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
     return st;
 }
 
+// ------------------------------------------------ solve without allocation
+// The work blocks of phicomb_solve_static live in this file-scope device
+// array (one copy per device the library runs on, kept until the process
+// ends).  In host code its name is only a stand-in for the device symbol:
+// the device address comes from hipGetSymbolAddress, taken once per device
+// at the first call with that device current, and only that address is
+// ever passed to kernels or copies.  The same first call creates the two
+// timing events of the device.  Calls on one device share the array; they
+// are serialised here (a call returns when its result is written), so
+// calls that would overlap on one device wait for each other.
+constexpr size_t kScratchBytes = (size_t)PHICOMB_STATIC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+    std::mutex mu;          // serialises the calls on this device
+    bool ready = false;
+    void *ptr = nullptr;    // device address of this device's scratch
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+StaticSlot g_static[kMaxDevices];
+}  // namespace
+
+}  // namespace phc
+
+extern "C" int phicomb_solve_static(phicomb_op op, const phicomb_params_t *prm, int p, int r,
+                                    const double *t, const double *beta, const void *V,
+                                    double tol, int precision, void *W, void *stream,
+                                    phicomb_stats_t *stats) {
+    using namespace phc;
+    if (solve_check_args(op, prm, p, r, t, beta, V, tol, precision, W) != PHICOMB_OK)
+        return PHICOMB_EINVAL;
+    const size_t need = solve_workspace_bytes(op->dev.n, p, r, precision, op_lr_rank(op));
+    if (need > kScratchBytes)
+        return PHICOMB_EINVAL;   // the work blocks exceed the static array
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return PHICOMB_EDEVICE;
+    if (dev != op->device)
+        return PHICOMB_EINVAL;   // the operator lives on another device
+    StaticSlot &sl = g_static[dev];
+    std::lock_guard<std::mutex> g(sl.mu);
+    if (!sl.ready) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return PHICOMB_EDEVICE;
+        if (hipEventCreate(&sl.ev[0]) != hipSuccess || hipEventCreate(&sl.ev[1]) != hipSuccess)
+            return PHICOMB_EDEVICE;
+        sl.ptr = ptr;
+        sl.ready = true;
+    }
+    std::lock_guard<std::mutex> go(op->mu);
+    const int st = solve_run(op, prm, p, r, t, beta, V, tol, precision, W, (hipStream_t)stream,
+                             stats, sl.ptr, kScratchBytes, op->pinned, 0, sl.ev);
+    if (stats)
+        stats->status = st;
+    return st;
+}
+
+namespace phc {
+
 }  // namespace phc
