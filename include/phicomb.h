@@ -234,7 +234,9 @@ int64_t phicomb_request_bytes(int64_t n, int p, int r, int precision);
  * (and with them the rows each thread owns) and lists chosen from a cost
  * model of one Taylor term (phicomb_batch_model) and the expected term count
  * of every instance (s_int steps of the length tol implies), so that the
- * predicted finishing time of the last group is smallest.  The launch is
+ * predicted finishing time of the last group is smallest: every instance
+ * gets the fewest workgroups that meet a trial makespan and joins, first fit,
+ * the smallest group of at least that size with time left.  The launch is
  * captured into a HIP graph and replayed by every run (recaptured when a
  * refit of the model changes the schedule).
  *   items     [count] solves: same fields as phicomb_solve; every operator of
@@ -275,9 +277,12 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
 /* The plan's cost model of one Taylor term on G workgroups, in microseconds:
  *   (G = 1 ? m[0] : m[1] + m[2] G) + ceil(n / (512 G)) (m[3] + m[4] 2r),
  * an exchange latency plus the rounds of rows each thread works through one
- * after another.  Every successful run refits it by least squares from the
- * device clocks of its instances and rebuilds the schedule when the refit
- * predicts a makespan 10 % below the measured one.  get (optional, 5 doubles)
+ * after another.  Every successful run refits it from the device clocks of
+ * its instances (the per-round constants by least squares over instances of
+ * 4 or more rounds, then the exchange constants from the remainders of
+ * instances of few rounds, where the exchange dominates) and
+ * rebuilds the schedule when the refit predicts a makespan 10 % below the
+ * measured one.  get (optional, 5 doubles)
  * receives the current model; set (optional, 5 non-negative doubles, e.g. a
  * model saved from an earlier plan by an autotuner) replaces it and rebuilds
  * the schedule (EINVAL for a negative or non-finite value). */
@@ -287,6 +292,11 @@ int phicomb_batch_model(phicomb_batch b, double *get, const double *set);
  * before the refit (with the run's measured term counts), and after it. */
 int phicomb_batch_fit(phicomb_batch b, double *measured_ms, double *predicted_ms_before,
                       double *predicted_ms_after);
+
+/* Per instance of the last run (optional arrays of count entries): its
+ * duration in microseconds from the device clock, and the workgroups of the
+ * group that ran it (the data the cost model is fitted to). */
+int phicomb_batch_times(phicomb_batch b, double *us, int *group_size);
 
 int phicomb_batch_destroy(phicomb_batch b);
 

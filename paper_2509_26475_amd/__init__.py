@@ -101,6 +101,7 @@ def _lib():
             "phicomb_batch_destroy": ([P], I32),
             "phicomb_batch_model": ([P, P, P], I32),
             "phicomb_batch_fit": ([P, P, P, P], I32),
+            "phicomb_batch_times": ([P, P, P], I32),
             "phicomb_exprk4s6": ([P, P, P, D, I32, D, I32, P, P, P], I32),
             "phicomb_solve_series": ([P, I32, I32, P, P, P, D, P, P, P], I32),
             "phicomb_op_apply": ([P, P, I32, D, P, P, P], I32),
@@ -360,6 +361,14 @@ def phicomb_batch_fit(b) -> dict:
            "phicomb_batch_fit")
     return {"measured_ms": m.value, "predicted_ms_before": p0.value,
             "predicted_ms_after": p1.value}
+
+
+def phicomb_batch_times(b, count: int):
+    """Per instance of the last run: (microseconds, workgroups of its group)."""
+    us = (C.c_double * count)()
+    gs = (C.c_int * count)()
+    _check(_lib().phicomb_batch_times(b, us, gs), "phicomb_batch_times")
+    return list(us), list(gs)
 
 
 def phicomb_batch_info(b) -> dict:

@@ -15,7 +15,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -80,10 +79,10 @@ struct ItemCost {
 // instances), and the autotuner keeps the fitted model on disk.
 struct Model {
     double e1 = 1.5;     // single-workgroup exchange (us)
-    double e2 = 3.0;     // grid exchange (us)
-    double g2 = 0.006;   // growth of the grid exchange per workgroup (us)
-    double l0 = 0.6;     // one round of rows (us)
-    double l1 = 0.1;     // one round of rows, per column (us)
+    double e2 = 4.0;     // grid exchange (us)
+    double g2 = 0.03;    // growth of the grid exchange per workgroup (us)
+    double l0 = 0.5;     // one round of rows (us)
+    double l1 = 1.2;     // one round of rows, per column (us)
 };
 static thread_local Model t_model;
 
@@ -105,8 +104,11 @@ struct Schedule {
 };
 
 // Smallest predicted makespan M with a schedule of at most cap workgroups:
-// every instance gets the fewest workgroups that finish it within M; those
-// needing one are packed longest-first onto single workgroups (first fit).
+// every instance, longest first, gets the fewest workgroups that finish it
+// within M, and joins the smallest existing group of at least that size that
+// still finishes within M (first fit), else opens a group of its own.  A
+// group runs its instances one after another, so a workgroup that an early
+// instance leaves idle takes later ones instead of waiting for the launch end.
 static bool schedule_for(const std::vector<ItemCost> &c, int cap, double M, Schedule &out) {
     const int count = (int)c.size();
     std::vector<int> order(count);
@@ -114,43 +116,32 @@ static bool schedule_for(const std::vector<ItemCost> &c, int cap, double M, Sche
     std::sort(order.begin(), order.end(),
               [&](int a, int b) { return cost_us(c[a], 1) > cost_us(c[b], 1); });
     Schedule s;
-    std::vector<double> load;   // single-workgroup groups
-    std::vector<int> single_group;
+    std::vector<double> load;   // per group
     for (int it : order) {
         int G = 1;
         while (G < c[it].gmax && cost_us(c[it], G) > M)
             ++G;
-        if (cost_us(c[it], G) > M && G == c[it].gmax && G > 1) {
-            // cannot meet M even with every useful workgroup
-            return false;
-        }
-        if (G > 1) {
-            s.gsize.push_back(G);
-            s.glist.push_back({it});
-            s.wgs += G;
-            continue;
-        }
-        const double t = cost_us(c[it], 1);
+        if (cost_us(c[it], G) > M)
+            return false;   // cannot meet M even with every useful workgroup
         int best = -1;
-        for (size_t k = 0; k < load.size(); ++k)
-            if (load[k] + t <= M) {
-                best = (int)k;
-                break;
-            }
-        if (best < 0) {
-            if (t > M)
-                return false;
-            load.push_back(0.0);
-            s.gsize.push_back(1);
-            s.glist.push_back({});
-            single_group.push_back((int)s.gsize.size() - 1);
-            s.wgs += 1;
-            best = (int)load.size() - 1;
+        for (size_t g = 0; g < s.gsize.size(); ++g) {
+            const int gs = s.gsize[g];
+            if (gs < G || (best >= 0 && gs >= s.gsize[best]))
+                continue;
+            if (load[g] + cost_us(c[it], gs) <= M)
+                best = (int)g;
         }
-        load[best] += t;
-        s.glist[single_group[best]].push_back(it);
-        if (s.wgs > cap)
-            return false;
+        if (best < 0) {
+            s.gsize.push_back(G);
+            s.glist.push_back({});
+            load.push_back(0.0);
+            s.wgs += G;
+            if (s.wgs > cap)
+                return false;
+            best = (int)s.gsize.size() - 1;
+        }
+        load[best] += cost_us(c[it], s.gsize[best]);
+        s.glist[best].push_back(it);
     }
     if (s.wgs > cap)
         return false;
@@ -315,60 +306,81 @@ int build_plan(phicomb_batch b) {
     return PHICOMB_OK;
 }
 
-// Least squares for the model's five constants from per-instance samples
-// (features: single workgroup, grid, grid size, rounds, rounds x columns; the
-// measured microseconds per term), by the normal equations with a tiny ridge.
-// Constants of features that no sample exercises keep their old values; the
-// fit is rejected if any fitted constant comes out negative or non-finite.
-bool fit_model(const std::vector<std::array<double, 5>> &x, const std::vector<double> &y,
-               Model &m) {
-    constexpr int K = 5;
-    double a[K][K + 1] = {};
-    bool used[K] = {};
-    for (size_t s = 0; s < x.size(); ++s)
-        for (int i = 0; i < K; ++i) {
-            if (x[s][i] != 0.0)
-                used[i] = true;
-            for (int j = 0; j < K; ++j)
-                a[i][j] += x[s][i] * x[s][j];
-            a[i][K] += x[s][i] * y[s];
-        }
-    if (x.size() < 3)
+// The model's constants from per-instance samples (workgroups G, rounds,
+// columns, measured microseconds per term), in two stages so that every
+// constant stays physical: the per-round constants (l0, l1) by least squares
+// over the samples whose rounds dominate (4 or more rounds), then the
+// exchange constants from what remains: e1 the median remainder of the
+// single-workgroup samples of at most 4 rounds, (e2, g2) a least-squares
+// line in G through the remainders of the grid samples of at most 2 rounds
+// (where the exchange is a large part of a term).  Constants without samples keep their
+// values; all are clamped to small positive floors.
+struct Sample {
+    double G, rounds, cols, us;
+};
+
+static bool lsq2(const std::vector<double> &x1, const std::vector<double> &x2,
+                 const std::vector<double> &y, double &a, double &b) {
+    double s11 = 0, s12 = 0, s22 = 0, s1y = 0, s2y = 0;
+    for (size_t k = 0; k < y.size(); ++k) {
+        s11 += x1[k] * x1[k];
+        s12 += x1[k] * x2[k];
+        s22 += x2[k] * x2[k];
+        s1y += x1[k] * y[k];
+        s2y += x2[k] * y[k];
+    }
+    const double det = s11 * s22 - s12 * s12;
+    if (y.size() < 3 || !(std::fabs(det) > 1e-12 * (s11 * s22 + 1e-300)))
         return false;
-    double tr = 0.0;
-    for (int i = 0; i < K; ++i)
-        tr += a[i][i];
-    for (int i = 0; i < K; ++i)
-        a[i][i] += 1e-9 * tr + (used[i] ? 0.0 : 1.0);
-    for (int c = 0; c < K; ++c) {   // Gaussian elimination with partial pivoting
-        int piv = c;
-        for (int r = c + 1; r < K; ++r)
-            if (std::fabs(a[r][c]) > std::fabs(a[piv][c]))
-                piv = r;
-        if (!(std::fabs(a[piv][c]) > 0.0))
-            return false;
-        for (int j = 0; j <= K; ++j)
-            std::swap(a[c][j], a[piv][j]);
-        for (int r = 0; r < K; ++r) {
-            if (r == c)
-                continue;
-            const double f = a[r][c] / a[c][c];
-            for (int j = c; j <= K; ++j)
-                a[r][j] -= f * a[c][j];
+    a = (s1y * s22 - s2y * s12) / det;
+    b = (s2y * s11 - s1y * s12) / det;
+    return std::isfinite(a) && std::isfinite(b);
+}
+
+static double median(std::vector<double> v) {
+    const size_t h = v.size() / 2;
+    std::nth_element(v.begin(), v.begin() + h, v.end());
+    return v[h];
+}
+
+bool fit_model(const std::vector<Sample> &smp, Model &m) {
+    Model out = m;
+    {
+        std::vector<double> x1, x2, y;
+        for (const Sample &s : smp)
+            if (s.rounds >= 4.0) {
+                x1.push_back(s.rounds);
+                x2.push_back(s.rounds * s.cols);
+                y.push_back(s.us);
+            }
+        double a, b;
+        if (lsq2(x1, x2, y, a, b)) {
+            out.l0 = std::max(a, 0.05);
+            out.l1 = std::max(b, 0.05);
         }
     }
-    double v[K];
-    for (int i = 0; i < K; ++i) {
-        v[i] = a[i][K] / a[i][i];
-        if (used[i] && !(v[i] >= 0.0 && std::isfinite(v[i])))
-            return false;
+    std::vector<double> r1, r2, g2;
+    for (const Sample &s : smp) {
+        const double rest = s.us - s.rounds * (out.l0 + out.l1 * s.cols);
+        if (s.G == 1.0 && s.rounds <= 4.0)
+            r1.push_back(rest);
+        else if (s.G > 1.0 && s.rounds <= 2.0) {
+            r2.push_back(rest);
+            g2.push_back(s.G);
+        }
     }
-    Model out = m;
-    if (used[0]) out.e1 = v[0];
-    if (used[1]) out.e2 = v[1];
-    if (used[2]) out.g2 = v[2];
-    if (used[3]) out.l0 = v[3];
-    if (used[4]) out.l1 = v[4];
+    if (!r1.empty())
+        out.e1 = std::max(median(r1), 0.5);
+    if (!r2.empty()) {
+        std::vector<double> ones(r2.size(), 1.0);
+        double a, b;
+        if (lsq2(ones, g2, r2, a, b)) {
+            out.e2 = std::max(a, 0.5);
+            out.g2 = std::max(b, 0.0);
+        } else {
+            out.e2 = std::max(median(r2), 0.5);
+        }
+    }
     m = out;
     return true;
 }
@@ -390,8 +402,7 @@ static double predicted_ms(phicomb_batch b) {
 // when that predicts a makespan 10 % below the run just measured.
 void tune(phicomb_batch b, double measured_ms) {
     b->runs += 1;
-    std::vector<std::array<double, 5>> x;
-    std::vector<double> y;
+    std::vector<Sample> smp;
     std::vector<int> group_of(b->count, 0);
     for (int g = 0; g < b->ng; ++g)
         for (int it : b->sched.glist[g])
@@ -405,15 +416,12 @@ void tune(phicomb_batch b, double measured_ms) {
         if (!(us > 0.0))
             continue;
         const int G = b->sched.gsize[group_of[it]];
-        const double rr = rounds(b->cost[it], G);
-        x.push_back({G == 1 ? 1.0 : 0.0, G > 1 ? 1.0 : 0.0, G > 1 ? (double)G : 0.0, rr,
-                     rr * b->cost[it].cols});
-        y.push_back(us / terms);
+        smp.push_back({(double)G, rounds(b->cost[it], G), b->cost[it].cols, us / terms});
     }
     b->last_measured_ms = measured_ms;
     b->last_predicted_ms = predicted_ms(b);   // this run's plan, term counts now measured
     Model m = b->model;
-    if (fit_model(x, y, m))
+    if (fit_model(smp, m))
         b->model = m;
     b->refit_predicted_ms = predicted_ms(b);
     t_model = b->model;
@@ -701,6 +709,22 @@ int phicomb_batch_fit(phicomb_batch b, double *measured_ms, double *predicted_ms
         *predicted_ms_before = b->last_predicted_ms;
     if (predicted_ms_after)
         *predicted_ms_after = b->refit_predicted_ms;
+    return PHICOMB_OK;
+}
+
+int phicomb_batch_times(phicomb_batch b, double *us, int *group_size) {
+    if (!b)
+        return PHICOMB_EINVAL;
+    std::vector<int> group_of(b->count, 0);
+    for (int g = 0; g < b->ng; ++g)
+        for (int it : b->sched.glist[g])
+            group_of[it] = g;
+    for (int it = 0; it < b->count; ++it) {
+        if (us)
+            us[it] = (double)(b->ts_host[2 * it + 1] - b->ts_host[2 * it]) / b->clock_khz * 1e3;
+        if (group_size)
+            group_size[it] = b->sched.gsize[group_of[it]];
+    }
     return PHICOMB_OK;
 }
 

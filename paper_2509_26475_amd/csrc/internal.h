@@ -131,8 +131,9 @@ enum : int {
     kLnGroup = 4,        // 16 group counters
     kLnGroupGen = 20,    // 16 group generations
     kLnGroupSize = 36,   // 16 group sizes
-    kLnMax = 52,         // 3 rotating lines of maxima folded into the barrier
 };
+
+constexpr int kRedMax = 4;   // values one exchange reduces at most (lines of 4 u64)
 
 struct GridSync {
     unsigned *bar;
@@ -209,19 +210,7 @@ __device__ __forceinline__ bool grid_setup(GridSync &gs, unsigned *bar, int *ok_
     return *ok_lds != 0;
 }
 
-// Barrier over the grid.  With nv > 0 it also reduces nv non-negative
-// doubles (vals, valid in thread 0: this workgroup's maxima) to their maximum
-// over all workgroups, left in res (LDS, nv entries) for every thread.  The
-// maxima ride on the arrival: each workgroup applies an agent-scope 64-bit
-// atomic max to the line of this barrier (non-negative doubles order like
-// their bit patterns; a NaN, positive or negative, compares above every
-// number, so it wins as in nmax) and waits for it before it arrives; after
-// the barrier one load per value returns the result.  Barrier g uses line
-// kLnMax + g % 3; the last arrival at the top of barrier g clears line
-// (g + 1) % 3, which every workgroup has finished reading (it was last read
-// after barrier g - 2) and nobody writes before passing barrier g.
-__device__ __forceinline__ bool grid_sync_impl(GridSync &gs, int *ok_lds, int nv,
-                                               const double *vals, double *res) {
+__device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
     wait_own_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -230,12 +219,6 @@ __device__ __forceinline__ bool grid_sync_impl(GridSync &gs, int *ok_lds, int nv
         unsigned *bar = gs.bar;
         unsigned *gc = bar + kLineU * (kLnGroup + gs.xcc);
         unsigned *gg = bar + kLineU * (kLnGroupGen + gs.xcc);
-        unsigned long long *line =
-            (unsigned long long *)(bar + kLineU * (kLnMax + g % 3u));
-        for (int j = 0; j < nv; ++j)
-            __hip_atomic_fetch_max(line + j, (unsigned long long)__double_as_longlong(vals[j]),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(0);   // the maxima are performed before the arrival
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         // The counters only ever grow (modulo 2^32): arrival number
         // (g+1)*size - 1 closes generation g.  Nothing is reset, so an early
@@ -246,16 +229,9 @@ __device__ __forceinline__ bool grid_sync_impl(GridSync &gs, int *ok_lds, int nv
             l2_writeback();
             const unsigned top = __hip_atomic_fetch_add(bar + kLineU * kLnTop, 1u,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (top + 1u == (g + 1u) * gs.ngroups) {
-                unsigned long long *next =
-                    (unsigned long long *)(bar + kLineU * (kLnMax + (g + 1u) % 3u));
-                for (int j = 0; j < 4; ++j)
-                    __hip_atomic_exchange(next + j, 0ull, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_s_waitcnt(0);   // cleared before the generation opens
+            if (top + 1u == (g + 1u) * gs.ngroups)
                 __hip_atomic_fetch_add(bar + kLineU * kLnTopGen, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-            }
             if (!spin_until_ne(bar + kLineU * kLnTopGen, g))
                 ok = 0;
             l2_invalidate();
@@ -265,9 +241,6 @@ __device__ __forceinline__ bool grid_sync_impl(GridSync &gs, int *ok_lds, int nv
                 ok = 0;
             l2_invalidate();   // this CU's L1 (and non-coherent L2 lines)
         }
-        for (int j = 0; j < nv; ++j)
-            res[j] = __longlong_as_double((long long)__hip_atomic_load(
-                line + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         gs.gen = g + 1;
         *ok_lds = ok;
     }
@@ -275,46 +248,73 @@ __device__ __forceinline__ bool grid_sync_impl(GridSync &gs, int *ok_lds, int nv
     return *ok_lds != 0;
 }
 
-__device__ __forceinline__ bool grid_sync(GridSync &gs, int *ok_lds) {
-    return grid_sync_impl(gs, ok_lds, 0, nullptr, nullptr);
-}
-
-// Maximum of NV non-negative values over the whole grid, left in every
-// thread's v: the workgroup's maximum (wave shuffles, then the waves through
-// red in LDS) is folded into the barrier's arrival (grid_sync_impl).  res:
-// LDS scratch of NV doubles.
+// Workgroup max of NV values into part[bid*kRedMax + j] (plain stores,
+// published by the next grid_sync); bid is the workgroup's index within its
+// grid.  (Folding the maxima into the barrier's arrival as agent-scope
+// atomics was measured slower: the atomics' round trip lies on the
+// barrier's critical path.)
 template <int NV, int NT>
-__device__ __forceinline__ bool grid_max(GridSync &gs, int *ok_lds, double (&v)[NV],
-                                         double (*red)[2], double *res) {
+__device__ __forceinline__ void store_partials(double (&v)[NV], double *part,
+                                               double (*red)[kRedMax], unsigned bid) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
         v[j] = wave_max(v[j]);
-    __syncthreads();   // every wave has finished reading res from the last exchange
+    __syncthreads();   // every wave has finished reading red from the last exchange
     if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             red[wave][j] = v[j];
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double m = red[0][j];
+            for (int w = 1; w < NT / 64; ++w)
+                m = nmax(m, red[w][j]);
+            part[bid * kRedMax + j] = m;
+        }
+    }
+}
+
+// Max over all workgroups' partials, after grid_sync; every thread gets it.
+template <int NV, int NT>
+__device__ __forceinline__ void load_partials(const double *part, unsigned nblocks,
+                                              double (&out)[NV], double (*red)[kRedMax]) {
     double m[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        m[j] = red[0][j];
-        for (int w = 1; w < NT / 64; ++w)
-            m[j] = nmax(m[j], red[w][j]);
+    for (int j = 0; j < NV; ++j)
+        m[j] = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += NT) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            m[j] = nmax(m[j], part[b * kRedMax + j]);
     }
-    const bool ok = grid_sync_impl(gs, ok_lds, NV, m, res);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
-        v[j] = res[j];
-    return ok;
+        m[j] = wave_max(m[j]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            red[wave][j] = m[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double r = red[0][j];
+        for (int w = 1; w < NT / 64; ++w)
+            r = nmax(r, red[w][j]);
+        out[j] = r;
+    }
 }
 
 // Max of NV values over one workgroup, left in every thread (a grid of a
 // single workgroup needs no exchange through memory).
 template <int NV, int NT>
-__device__ __forceinline__ void workgroup_max(double (&v)[NV], double (*red)[2]) {
+__device__ __forceinline__ void workgroup_max(double (&v)[NV], double (*red)[kRedMax]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
@@ -410,6 +410,14 @@ __device__ __forceinline__ T ld_col(const T *__restrict__ base, unsigned idx) {
     return *(const T *)((const char *)base + idx * (unsigned)sizeof(T));
 }
 
+// a b + c with one rounding, in the accumulation type.  Stencil rows are
+// accumulated with explicit fused multiply-adds in a fixed order (centre
+// product, then -x, +x, -y, +y, -z, +z) so that a row's value is the same in
+// every kernel that computes it (one row per lane or two), whatever the
+// compiler would contract on its own.
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // y[j] = (A X)(i, col0+j) - shift * X(i, col0+j), j < NC, with X of element
 // type TX and the products accumulated in TA (double, or float for the
 // reduced-precision terms).  X is column-major: column c at X + c*ld.
@@ -432,14 +440,14 @@ __device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
             const TA w = (TA)A.c[1];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += w * (TA)ld_col(cb[j], q);
+                y[j] = fmadd(w, (TA)ld_col(cb[j], q), y[j]);
         }
         if (rc.mask & 2u) {
             const unsigned q = i + 1u;
             const TA w = (TA)rc.cxp;
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += w * (TA)ld_col(cb[j], q);
+                y[j] = fmadd(w, (TA)ld_col(cb[j], q), y[j]);
         }
         const unsigned sy = (unsigned)A.nx;
         if (rc.mask & 4u) {
@@ -447,14 +455,14 @@ __device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
             const TA w = (TA)A.c[3];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += w * (TA)ld_col(cb[j], q);
+                y[j] = fmadd(w, (TA)ld_col(cb[j], q), y[j]);
         }
         if (rc.mask & 8u) {
             const unsigned q = i + sy;
             const TA w = (TA)A.c[4];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += w * (TA)ld_col(cb[j], q);
+                y[j] = fmadd(w, (TA)ld_col(cb[j], q), y[j]);
         }
         const unsigned sz = (unsigned)A.nx * (unsigned)A.ny;
         if (rc.mask & 16u) {
@@ -462,14 +470,14 @@ __device__ __forceinline__ void apply_cols(const DevOp &A, const RowCtx &rc,
             const TA w = (TA)A.c[5];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += w * (TA)ld_col(cb[j], q);
+                y[j] = fmadd(w, (TA)ld_col(cb[j], q), y[j]);
         }
         if (rc.mask & 32u) {
             const unsigned q = i + sz;
             const TA w = (TA)A.c[6];
 #pragma unroll
             for (int j = 0; j < NC; ++j)
-                y[j] += w * (TA)ld_col(cb[j], q);
+                y[j] = fmadd(w, (TA)ld_col(cb[j], q), y[j]);
         }
     } else {
 #pragma unroll
@@ -571,30 +579,30 @@ __device__ __forceinline__ void apply_pair(const DevOp &A, const PairCtx &pc,
         // -y, +y, -z, +z), so that a row's value does not depend on whether
         // it was computed alone or in a pair
         TA a0 = cc * (TA)v.x;
-        a0 += wl0 * (TA)l;
-        a0 += wr0 * (TA)v.y;
+        a0 = fmadd(wl0, (TA)l, a0);
+        a0 = fmadd(wr0, (TA)v.y, a0);
         TA a1 = cc * (TA)v.y;
-        a1 += wl1 * (TA)v.x;
-        a1 += wr1 * (TA)r;
+        a1 = fmadd(wl1, (TA)v.x, a1);
+        a1 = fmadd(wr1, (TA)r, a1);
         if (pc.mask & 1u) {
             const auto w = ld_pair(b, i - sy);
-            a0 += (TA)A.c[3] * (TA)w.x;
-            a1 += (TA)A.c[3] * (TA)w.y;
+            a0 = fmadd((TA)A.c[3], (TA)w.x, a0);
+            a1 = fmadd((TA)A.c[3], (TA)w.y, a1);
         }
         if (pc.mask & 2u) {
             const auto w = ld_pair(b, i + sy);
-            a0 += (TA)A.c[4] * (TA)w.x;
-            a1 += (TA)A.c[4] * (TA)w.y;
+            a0 = fmadd((TA)A.c[4], (TA)w.x, a0);
+            a1 = fmadd((TA)A.c[4], (TA)w.y, a1);
         }
         if (pc.mask & 4u) {
             const auto w = ld_pair(b, i - sz);
-            a0 += (TA)A.c[5] * (TA)w.x;
-            a1 += (TA)A.c[5] * (TA)w.y;
+            a0 = fmadd((TA)A.c[5], (TA)w.x, a0);
+            a1 = fmadd((TA)A.c[5], (TA)w.y, a1);
         }
         if (pc.mask & 8u) {
             const auto w = ld_pair(b, i + sz);
-            a0 += (TA)A.c[6] * (TA)w.x;
-            a1 += (TA)A.c[6] * (TA)w.y;
+            a0 = fmadd((TA)A.c[6], (TA)w.x, a0);
+            a1 = fmadd((TA)A.c[6], (TA)w.y, a1);
         }
         y0[j] = a0;
         y1[j] = a1;

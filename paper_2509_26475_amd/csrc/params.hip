@@ -25,7 +25,8 @@
 
 namespace phc {
 
-constexpr int kPNT = 512;          // threads per workgroup
+constexpr int kPNT = 512;          // threads per workgroup (register-cached CSR rows)
+constexpr int kPNTWide = 1024;     // threads per workgroup (every other operator)
 constexpr int kParamRows = 4;      // rows per thread of the register-cached CSR variant
 constexpr int kPMaxGrid = 4096;
 
@@ -110,9 +111,9 @@ __device__ __forceinline__ double splitmix_unit(uint64_t seed, int64_t i) {
     return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-template <int KIND>
-__global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
-    __shared__ double wsc[kPNT / 64], wsq[kPNT / 64];
+template <int KIND, int NT>
+__device__ __forceinline__ void params_body(const ParamsArgs &P) {
+    __shared__ double wsc[NT / 64], wsq[NT / 64];
     __shared__ double coef[PHICOMB_MAX_M + 1];
     __shared__ double lrc[kLrRankMax];
     __shared__ int ok_lds;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     if constexpr (CACHED) {
 #pragma unroll
         for (int q = 0; q < kParamRows; ++q) {
-            const int64_t row = lo + tid + (int64_t)q * kPNT;
+            const int64_t row = lo + tid + (int64_t)q * NT;
             if (row < hi)
                 load_cached_row(A, row, crow[q]);
         }
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         double *pt = P.part + (size_t)(epoch & 1) * 2 * kPMaxGrid;
         if (tid == 0) {
             Ssq acc{wsc[0], wsq[0]};
-            for (int w = 1; w < kPNT / 64; ++w)
+            for (int w = 1; w < NT / 64; ++w)
                 acc = ssq_merge(acc, Ssq{wsc[w], wsq[w]});
             pt[blockIdx.x * 2] = acc.scale;
             pt[blockIdx.x * 2 + 1] = acc.ssq;
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         if (!grid_sync(gs, &ok_lds))
             alive = false;
         Ssq acc{0.0, 0.0};
-        for (unsigned b = tid; b < G; b += kPNT)
+        for (unsigned b = tid; b < G; b += NT)
             acc = ssq_merge(acc, Ssq{pt[b * 2], pt[b * 2 + 1]});
         acc = wave_ssq(acc);
         __syncthreads();
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         }
         __syncthreads();
         Ssq tot{wsc[0], wsq[0]};
-        for (int w = 1; w < kPNT / 64; ++w)
+        for (int w = 1; w < NT / 64; ++w)
             tot = ssq_merge(tot, Ssq{wsc[w], wsq[w]});
         ++epoch;
         return tot;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         __syncthreads();   // this workgroup's rows of x are written
         double *pt = P.lrpart + (size_t)(lr_epoch & 1) * 2 * lr_lo;
         const int rank = A.rank;
-        for (int k = wave; k < rank; k += kPNT / 64) {
+        for (int k = wave; k < rank; k += NT / 64) {
             DD acc{0.0, 0.0};
             for (int64_t row = lo + lane; row < hi; row += 64)
                 dd_fma(acc, A.lr_w[row * rank + k], x[row]);
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         }
         if (!grid_sync(gs, &ok_lds))
             return false;
-        for (int k = wave; k < rank; k += kPNT / 64) {
+        for (int k = wave; k < rank; k += NT / 64) {
             DD acc{0.0, 0.0};
             for (unsigned b = lane; b < G; b += 64)
                 acc = dd_add(acc, DD{pt[(size_t)k * kPMaxGrid + b],
@@ -234,10 +235,10 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
 
     // ---- V_0 = v / ||v||
     if (!P.have_v)
-        for (int64_t row = lo + tid; row < hi; row += kPNT)
+        for (int64_t row = lo + tid; row < hi; row += NT)
             basis[row] = splitmix_unit(P.seed, row);
     Ssq a{0.0, 0.0};
-    for (int64_t row = lo + tid; row < hi; row += kPNT)
+    for (int64_t row = lo + tid; row < hi; row += NT)
         ssq_add(a, basis[row]);
     const Ssq vs = exchange(a);
     const double nv = vs.scale * sqrt(vs.ssq);
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
                 finish(PHICOMB_EDEVICE, 0, 0, 0, 0, 0, 0, 0);
                 return;
             }
-            for (int64_t row = lo + tid; row < hi; row += kPNT) {
+            for (int64_t row = lo + tid; row < hi; row += NT) {
                 const double w = lr_row(row);
                 const double val = (k == 1) ? w / nv : w;   // A (v/||v||)
                 y[row] = val;
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
             }
         } else if constexpr (KIND == kDense) {
             // dense rows: one wave per row, lanes across the row, wave sum
-            for (int64_t row = lo + (tid >> 6); row < hi; row += kPNT / 64) {
+            for (int64_t row = lo + (tid >> 6); row < hi; row += NT / 64) {
                 const double *arow = A.dense + row * n;
                 double sum = 0.0;
                 for (int64_t c = tid & 63; c < n; c += 64)
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         } else if constexpr (CACHED) {
 #pragma unroll
             for (int q = 0; q < kParamRows; ++q) {
-                const int64_t row = lo + tid + (int64_t)q * kPNT;
+                const int64_t row = lo + tid + (int64_t)q * NT;
                 if (row < hi) {
                     double w[1];
                     apply_cached<1>(crow[q], (unsigned)row, x, n, 0, 0.0, w);
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
                 }
             }
         } else {
-            for (int64_t row = lo + tid; row < hi; row += kPNT) {
+            for (int64_t row = lo + tid; row < hi; row += NT) {
                 const RowCtx rc = row_ctx<KIND>(A, row);
                 double w[1];
                 apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         }
         if (k == 1) {
             L1 = Lk;
-            for (int64_t row = lo + tid; row < hi; row += kPNT)   // nobody reads V_0 again
+            for (int64_t row = lo + tid; row < hi; row += NT)   // nobody reads V_0 again
                 basis[row] = basis[row] / nv;
         }
         if (Lk != Lk) {
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     for (int j = 1; j <= r; ++j) {
         const double sc = exp(-(double)j * ls0);
         double *v = col(j);
-        for (int64_t row = lo + tid; row < hi; row += kPNT)
+        for (int64_t row = lo + tid; row < hi; row += NT)
             v[row] = v[row] * sc;
     }
     for (int k = r + 1; k <= m; ++k) {
@@ -368,10 +369,10 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
             return;
         }
         if constexpr (KIND == kLowRank) {
-            for (int64_t row = lo + tid; row < hi; row += kPNT)
+            for (int64_t row = lo + tid; row < hi; row += NT)
                 y[row] = lr_row(row) / s0;
         } else if constexpr (KIND == kDense) {
-            for (int64_t row = lo + (tid >> 6); row < hi; row += kPNT / 64) {
+            for (int64_t row = lo + (tid >> 6); row < hi; row += NT / 64) {
                 const double *arow = A.dense + row * n;
                 double sum = 0.0;
                 for (int64_t c = tid & 63; c < n; c += 64)
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
         } else if constexpr (CACHED) {
 #pragma unroll
             for (int q = 0; q < kParamRows; ++q) {
-                const int64_t row = lo + tid + (int64_t)q * kPNT;
+                const int64_t row = lo + tid + (int64_t)q * NT;
                 if (row < hi) {
                     double w[1];
                     apply_cached<1>(crow[q], (unsigned)row, x, n, 0, 0.0, w);
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
                 }
             }
         } else {
-            for (int64_t row = lo + tid; row < hi; row += kPNT) {
+            for (int64_t row = lo + tid; row < hi; row += NT) {
                 const RowCtx rc = row_ctx<KIND>(A, row);
                 double w[1];
                 apply_cols<KIND, 1>(A, rc, x, n, 0, 0.0, w);
@@ -412,11 +413,25 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
             coef[tid] = P.binom[tid] * pw;
         }
         __syncthreads();
+        // eight powers per step in flight: the pass streams (m+1) n doubles,
+        // so it is bound by how many loads are outstanding; each row still
+        // sums its powers in ascending k
         Ssq acc{0.0, 0.0};
-        for (int64_t row = lo + tid; row < hi; row += kPNT) {
+        for (int64_t row = lo + tid; row < hi; row += NT) {
+            const double *b = basis + row;
             double y = 0.0;
-            for (int k = 0; k <= m; ++k)
-                y += coef[k] * basis[(int64_t)k * n + row];
+            int k = 0;
+            for (; k + 8 <= m + 1; k += 8) {
+                double bk[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    bk[j] = b[(int64_t)(k + j) * n];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    y = fma(coef[k + j], bk[j], y);
+            }
+            for (; k <= m; ++k)
+                y = fma(coef[k], b[(int64_t)k * n], y);
             ssq_add(acc, y);
         }
         const Ssq tot = exchange(acc);
@@ -492,6 +507,20 @@ __global__ __launch_bounds__(kPNT) void params_kernel(ParamsArgs P) {
     finish(PHICOMB_OK, r, s0, x, fx, -x * s0, 0.0, evals);
 }
 
+// Sixteen waves a workgroup (at most 128 registers a lane) keep enough loads
+// of the objective's pass in flight with one workgroup per compute unit; the
+// register-cached CSR variant holds its rows instead and runs eight.
+template <int KIND>
+__global__ __launch_bounds__(kPNTWide) void params_kernel(ParamsArgs P) {
+    params_body<KIND, kPNTWide>(P);
+}
+
+__global__ __launch_bounds__(kPNT) void params_kernel_cached(ParamsArgs P) {
+    params_body<kCsrCached, kPNT>(P);
+}
+
+int params_nt(int kind) { return kind == kCsrCached ? kPNT : kPNTWide; }
+
 // ------------------------------------------------------------------ host
 namespace {
 double binom_double(int m, int k) {
@@ -509,7 +538,7 @@ const void *params_fn(int kind) {
     case kStencil: return (const void *)params_kernel<kStencil>;
     case kDense: return (const void *)params_kernel<kDense>;
     case kLowRank: return (const void *)params_kernel<kLowRank>;
-    case kCsrCached: return (const void *)params_kernel<kCsrCached>;
+    case kCsrCached: return (const void *)params_kernel_cached;
     default: return (const void *)params_kernel<kCsr>;
     }
 }
@@ -528,7 +557,7 @@ int max_params_grid(int kind, int device) {
     const void *fn = params_fn(kind);
     int per_cu = 0;
     hipDeviceProp_t prop;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPNT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, params_nt(kind), 0) != hipSuccess ||
         hipGetDeviceProperties(&prop, device) != hipSuccess || per_cu < 1)
         return 0;
     // one workgroup per CU: the barrier cost grows with the number of workgroups
@@ -595,8 +624,8 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     const int maxg = max_params_grid(op->dev.kind, op->device);
     if (maxg < 1)
         return PHICOMB_EDEVICE;
-    // dense rows are spread so that every wave has at most two of them
-    const int64_t rows_per_wg = (op->dev.kind == kDense) ? 16 : kPNT;
+    // dense rows are spread thinly (one a wave while the grid allows)
+    const int64_t rows_per_wg = (op->dev.kind == kDense) ? 16 : params_nt(op->dev.kind);
     const int64_t G = std::min<int64_t>(maxg, (n + rows_per_wg - 1) / rows_per_wg);
     const int held = round_xcd(G);   // at most ceil(G/8) of the grid lands on any XCD
     // short CSR rows and a chunk of at most kParamRows rows per thread: rows
@@ -614,7 +643,7 @@ int params_fp64(phicomb_op op, double tol, int m, const double *v, uint64_t seed
     } hold{op->device, held};
     params_sync_init<<<1, 256, 0, stream>>>(a.bar, a.out);
     void *args[] = {&a};
-    if (launch_persistent(fn, (unsigned)G, kPNT, args, stream) != hipSuccess)
+    if (launch_persistent(fn, (unsigned)G, params_nt(kind), args, stream) != hipSuccess)
         return PHICOMB_EDEVICE;
     if (hipMemcpyAsync(op->pinned, a.out, 8 * sizeof(double), hipMemcpyDeviceToHost, stream) !=
             hipSuccess ||

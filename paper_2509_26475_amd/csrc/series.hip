@@ -46,8 +46,7 @@ __global__ void series_sync_init(unsigned *bar, int *info) {
 
 template <int KIND, int R>
 __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
-    __shared__ double red[kNT / 64][2];
-    __shared__ double res[2];
+    __shared__ double red[kNT / 64][kRedMax];
     __shared__ double wk[kRMax][kPMax1];   // this term's weight of P_j[:, i] in column k
     __shared__ double rpow[kRMax];         // (t_k / tau)^j
     __shared__ double lrc[kLrVals];        // low rank: W^T P_j of the coming product
@@ -89,8 +88,11 @@ __global__ __launch_bounds__(kNT) void series_kernel(SeriesArgs P) {
             ++epoch;
             return true;
         }
-        if (!grid_max<2, kNT>(gs, &ok, v, red, res))
+        double *pt = P.part + (size_t)(epoch & 1) * kRedMax * kMaxGrid;
+        store_partials<2, kNT>(v, pt, red, bid);
+        if (!grid_sync(gs, &ok))
             return false;
+        load_partials<2, kNT>(pt, G, v, red);
         if constexpr (KIND == kLowRank)
             lr_gather(lr_part(), lr_lo, G, nlr, lrc);
         ++epoch;
@@ -253,7 +255,7 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
     const int P1 = p + 1;
 
     std::lock_guard<std::mutex> lk(op->mu);
-    const size_t sync = (size_t)kSyncBytes + sizeof(double) * 4 * kMaxGrid + 256;
+    const size_t sync = (size_t)kSyncBytes + sizeof(double) * 2 * kRedMax * kMaxGrid + 256;
     const int rank = op_lr_rank(op);
     const size_t lr = (rank > 0) ? sizeof(double) * 4 * (size_t)rank * P1 * kMaxGrid + 256 : 0;
     const size_t need = sync + sizeof(double) * 2 * (size_t)P1 * (size_t)n + lr;
@@ -281,7 +283,7 @@ extern "C" int phicomb_solve_series(phicomb_op op, int p, int r, const double *t
     char *base = (char *)op->ws.ptr;
     a.bar = (unsigned *)base;
     a.part = (double *)(base + kSyncBytes);
-    a.info = (int *)(base + kSyncBytes + sizeof(double) * 4 * kMaxGrid);
+    a.info = (int *)(base + kSyncBytes + sizeof(double) * 2 * kRedMax * kMaxGrid);
     a.X0 = (double *)(base + sync);
     a.X1 = a.X0 + (size_t)P1 * n;
     if (rank > 0)

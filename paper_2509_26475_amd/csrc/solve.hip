@@ -54,7 +54,7 @@ static int max_coresident(KernelFn fn, int device, int nt = kNT) {
     return total;
 }
 
-static size_t sync_bytes() { return (size_t)kSyncBytes + sizeof(double) * 4 * kMaxGrid + 256; }
+static size_t sync_bytes() { return (size_t)kSyncBytes + sizeof(double) * 2 * kRedMax * kMaxGrid + 256; }
 size_t solve_sync_bytes() { return sync_bytes(); }
 
 // Entries of W^T X exchanged per term for a low-rank operator: the S-series
@@ -229,7 +229,7 @@ int build_solve_args(phicomb_op op, const phicomb_params_t *prm, int p, int r, c
     char *base = (char *)ws;
     a.bar = (unsigned *)base;
     a.part = (double *)(base + kSyncBytes);
-    a.info = (int *)(base + kSyncBytes + sizeof(double) * 4 * kMaxGrid);
+    a.info = (int *)(base + kSyncBytes + sizeof(double) * 2 * kRedMax * kMaxGrid);
     double *d = (double *)(base + sync_bytes());
     a.S = d;
     d += (size_t)n * a.cS;

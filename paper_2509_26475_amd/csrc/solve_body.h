@@ -66,7 +66,7 @@ struct SolveArgs {
     double mix_tau;                     // tol / (10 u_fp32): FP32 term threshold
     double mix_lo, mix_hi;              // partial-sum norms for which FP32 terms are safe
     unsigned *bar;                      // sync area (kSyncBytes)
-    double *part;                       // [2][kMaxGrid][2] partial maxima
+    double *part;                       // [2][kMaxGrid][kRedMax] partial maxima
     double *lrpart;                     // low rank: [2][2][lrv][kMaxGrid] partial W^T X (hi, lo)
     int lrv;                            // low rank: rank * max(cS + r, 2r)
     int *info;                          // status, terms_S, terms_rec, max_terms_step
@@ -256,8 +256,7 @@ struct TypeTag {
 struct SolveShared {
     double Mk[kRMax][kPMax1][kPMax1];   // J_step^(k-1) / k!
     double Cj[kRMax][kPMax1][kPMax1];   // gam[i][b] * Mk[i][b][.]
-    double red[kMaxNT / 64][2];
-    double res[2];                      // grid-wide maxima of the last exchange
+    double red[kMaxNT / 64][kRedMax];
     double lrc[kLrVals];                // low rank: W^T X of the coming product
     int ok;
 };
@@ -396,8 +395,11 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             ++epoch;
             return true;
         }
-        if (!grid_max<NV, NT>(gs, &sh.ok, v, red, sh.res))
+        double *pt = P.part + (size_t)(epoch & 1) * kRedMax * kMaxGrid;
+        store_partials<NV, NT>(v, pt, red, bid);
+        if (!grid_sync(gs, &sh.ok))
             return false;
+        load_partials<NV, NT>(pt, G, v, red);
         if constexpr (KIND == kLowRank)
             lr_gather(lr_part(), lr_lo, G, nlr, sh.lrc);
         ++epoch;
@@ -510,7 +512,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
 #pragma unroll
                 for (int bb = 1; bb < kPMax1; ++bb)
                     if (bb <= b)
-                        jt += Cj[i][bb][b] * vr[bb];
+                        jt = fmadd(Cj[i][bb][b], vr[bb], jt);
                 return jt;
             };
             if (pairs) {
@@ -545,13 +547,13 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                             } else {
                                 for (int bb = 1; bb <= b; ++bb) {
                                     const int pbb = p + 1 - bb;
-                                    j0 += Cj[i][bb][b] * P.V[i0 * P1 + pbb];
-                                    j1 += Cj[i][bb][b] * P.V[(i0 + 1) * P1 + pbb];
+                                    j0 = fmadd(Cj[i][bb][b], P.V[i0 * P1 + pbb], j0);
+                                    j1 = fmadd(Cj[i][bb][b], P.V[(i0 + 1) * P1 + pbb], j1);
                                 }
                             }
                             (void)pb;
-                            double u0 = ((double)y0[cc] * P.ts[i]) * rk + j0;
-                            double u1 = ((double)y1[cc] * P.ts[i]) * rk + j1;
+                            double u0 = fmadd((double)y0[cc] * P.ts[i], rk, j0);
+                            double u1 = fmadd((double)y1[cc] * P.ts[i], rk, j1);
                             const int64_t o = (int64_t)c * n + i0;
                             typename Vec2<TS>::type uv = {(TS)u0, (TS)u1};
                             *(typename Vec2<TS>::type *)(Un_ + o) = uv;
@@ -587,7 +589,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                     opr(row, q, Uo_, b * R, P.xi, y);
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
-                        double u = ((double)y[i] * P.ts[i]) * rk + jterm(i, b, vr);
+                        double u = fmadd((double)y[i] * P.ts[i], rk, jterm(i, b, vr));
                         const int64_t o = (int64_t)(b * R + i) * n + row;
                         const TS us = (TS)u;
                         Un_[o] = us;
