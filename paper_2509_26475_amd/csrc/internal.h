@@ -24,6 +24,10 @@ constexpr int kTermCap = 150;                 // Taylor terms per loop
 constexpr long kSpinLimit = 1L << 27;         // barrier wait bound (~10 s), then EDEVICE
 
 enum OpKind : int { kStencil = 0, kCsr = 1, kDense = 2, kCsrCached = 3, kLowRank = 4 };
+// Kernel-template kind only (never an operator's kind): a small dense
+// operator held in LDS, with the whole solve on one workgroup.
+constexpr int kDenseLds = 5;
+__host__ __device__ constexpr bool is_dense(int kind) { return kind == kDense || kind == kDenseLds; }
 
 // Low-rank operators A = U W^T: rank at most kLrRankMax.
 constexpr int kLrRankMax = 16;
@@ -56,11 +60,28 @@ struct DevOp {
 // stopping test and is reported.
 __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
+// v moved by one DPP step (control CTRL, rows ROWS): the source lane's value
+// where the step has one, v itself in the lanes it leaves alone.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_or_self(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false));
+}
+
+// Max over the wave's 64 lanes, returned in every lane: row shifts by 1, 2,
+// 4, 8 leave each 16-lane row's max in its last lane, two row broadcasts
+// carry them to lane 63, which is read back as a scalar.  (Max is order
+// free, so this equals any other reduction order, NaN included.)
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v = nmax(v, __shfl_xor(v, off, 64));
-    return v;
+    v = nmax(v, dpp_or_self<0x111, 0xF>(v));   // row_shr:1
+    v = nmax(v, dpp_or_self<0x112, 0xF>(v));   // row_shr:2
+    v = nmax(v, dpp_or_self<0x114, 0xF>(v));   // row_shr:4
+    v = nmax(v, dpp_or_self<0x118, 0xF>(v));   // row_shr:8
+    v = nmax(v, dpp_or_self<0x142, 0xA>(v));   // row_bcast:15 into rows 1, 3
+    v = nmax(v, dpp_or_self<0x143, 0xC>(v));   // row_bcast:31 into rows 2, 3
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -342,13 +363,14 @@ __device__ __forceinline__ void workgroup_max(double (&v)[NV], double (*red)[kRe
 // into PHICOMB_EDEVICE instead of a hang.  PHICOMB_LAUNCH=cooperative asks
 // the runtime for the co-residency guarantee instead.
 inline hipError_t launch_persistent(const void *fn, unsigned grid, unsigned block, void **args,
-                                    hipStream_t stream) {
+                                    hipStream_t stream, size_t shmem = 0) {
     static const bool coop = [] {
         const char *e = getenv("PHICOMB_LAUNCH");
         return e && e[0] == 'c';
     }();
-    return coop ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, stream)
-                : hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, stream);
+    return coop ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)shmem,
+                                             stream)
+                : hipLaunchKernel(fn, dim3(grid), dim3(block), args, shmem, stream);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a

@@ -122,10 +122,43 @@ void solve_grid_request(phicomb_op op, int *want, int *floor_g) {
     }
 }
 
+// Dynamic LDS a workgroup may hold on this device (0 if unknown).
+static int max_lds_per_block(int device) {
+    static std::mutex m;
+    static int cache[64] = {};
+    std::lock_guard<std::mutex> g(m);
+    int &c = cache[device & 63];
+    if (c == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+                hipSuccess ||
+            v < 0)
+            v = 0;
+        c = v + 1;   // 0 means not yet queried
+    }
+    return c - 1;
+}
+
 static KernelFn select_variant(phicomb_op op, int r, bool mix, int64_t wgs_needed1, int cap,
-                               int64_t *G, int *nt) {
+                               int64_t *G, int *nt, size_t *lds, int p) {
     *nt = kNT;
+    *lds = 0;
     if (op->dev.kind == kDense) {
+        if (!mix && cap >= 1 && op->dev.n <= kDenseLdsN) {
+            // everything in LDS on one workgroup when it fits
+            KernelFn f = pick_dense_lds(r);
+            hipFuncAttributes fa;
+            const size_t dyn = dense_lds_bytes(op->dev.n, (int64_t)(p + 1) * r, 2LL * r);
+            if (f && hipFuncGetAttributes(&fa, (const void *)f) == hipSuccess &&
+                fa.localSizeBytes <= kFrameOk &&
+                fa.sharedSizeBytes + dyn <= (size_t)max_lds_per_block(op->device) &&
+                hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)dyn) == hipSuccess) {
+                *G = 1;
+                *lds = dyn;
+                return f;
+            }
+        }
         KernelFn f = pick_dense(r);
         if (!f)
             return nullptr;
@@ -277,12 +310,14 @@ int solve_launch_held(phicomb_op op, const phicomb_params_t *prm, int p, int r, 
     const int64_t wgs_needed1 = (op->dev.n + kNT - 1) / kNT;
     int64_t G = 0;
     int nt = kNT;
-    KernelFn fn = select_variant(op, r, precision == PHICOMB_MIXED, wgs_needed1, slots, &G, &nt);
+    size_t lds = 0;
+    KernelFn fn =
+        select_variant(op, r, precision == PHICOMB_MIXED, wgs_needed1, slots, &G, &nt, &lds, p);
     if (!fn)
         return PHICOMB_EINVAL;
     solve_sync_init<<<1, 256, 0, stream>>>(a.bar, a.info);
     void *args[] = {&a};
-    if (launch_persistent((const void *)fn, (unsigned)G, nt, args, stream) != hipSuccess)
+    if (launch_persistent((const void *)fn, (unsigned)G, nt, args, stream, lds) != hipSuccess)
         return PHICOMB_EDEVICE;
     *info_dev = a.info;
     *s_int = a.s_int;
@@ -319,7 +354,8 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
         return PHICOMB_EDEVICE;
     int64_t G = 0;
     int nt = kNT;
-    KernelFn fn = select_variant(op, r, mix, wgs_needed1, granted, &G, &nt);
+    size_t lds = 0;
+    KernelFn fn = select_variant(op, r, mix, wgs_needed1, granted, &G, &nt, &lds, p);
     if (!fn) {
         cu_release(op->device, granted);
         return PHICOMB_EINVAL;
@@ -354,7 +390,7 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
     if (timed)
         hipEventRecord(e0, stream);
     void *args[] = {&a};
-    hipError_t le = launch_persistent((const void *)fn, (unsigned)G, nt, args, stream);
+    hipError_t le = launch_persistent((const void *)fn, (unsigned)G, nt, args, stream, lds);
     if (le != hipSuccess) {
         drop_events();
         return PHICOMB_EDEVICE;

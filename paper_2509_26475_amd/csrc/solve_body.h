@@ -137,6 +137,20 @@ struct DenseShared {
 
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 
+// Small dense operators (n <= kDenseLdsN) on one workgroup.  A stays in
+// registers for the whole solve: lane l of wave w holds row 16 w + l / 4,
+// columns k = 4 j + l % 4 (j < kDenseLdsJ, zero past n), so a product needs
+// no A traffic at all; the term blocks S, U0, U1 and E live in LDS, so a
+// Taylor term touches no global memory.  Products run on the vector ALUs
+// (two columns at a time, the four partial sums of a row added across the
+// lanes of a quad), which for the few columns of a term beats a 16-column
+// MFMA tile that FP64 fills at half rate on this chip.
+constexpr int kDenseLdsN = 112;
+constexpr int kDenseLdsJ = kDenseLdsN / 4;   // columns of A a lane holds
+struct DenseLdsShared {
+    double Y[kDenseLdsN][kDenseCols + 1];   // products of all rows
+};
+
 // Y[i][c] = sum_k A[lo+i][k] X[c n + k] - shift X[c n + lo + i],
 // i < hi - lo, c < ncols.  Every thread of the workgroup calls it.
 __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, int64_t n,
@@ -179,6 +193,51 @@ __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, in
         for (int ks = 0; ks < KS; ++ks)
             sum += ds.part[tile + ks * tiles][i & 15][c & 15];
         ds.Y[i][c] = sum - shift * X[(int64_t)c * n + lo + i];
+    }
+    __syncthreads();
+}
+
+// v summed over the four lanes of each quad (DPP quad permutations, the same
+// order in every lane: (v0 + v1) + (v2 + v3)).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double quad_sum(double v) {
+    v = v + dpp_f64<0xB1>(v);      // lanes q ^ 1
+    return v + dpp_f64<0x4E>(v);   // lanes q ^ 2
+}
+
+// Y[i][c] = sum_k A[i][k] X[c n + k] - shift X[c n + i] for i < n, c < ncols,
+// A in the registers areg (layout above), X in LDS.  X is read at a clamped
+// index past n (A is zero there).  Every thread of the workgroup calls it.
+__device__ __forceinline__ void dense_products_lds(const double (&areg)[kDenseLdsJ], int64_t n,
+                                                   const double *__restrict__ X, int ncols,
+                                                   double shift, DenseLdsShared &ds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = wave * 16 + (lane >> 2), q = lane & 3;
+    const int nm1 = (int)n - 1;
+    if (wave * 16 < n) {
+        for (int c0 = 0; c0 < ncols; c0 += 2) {
+            const double *x0 = X + (int64_t)c0 * n;
+            const double *x1 = X + (int64_t)min(c0 + 1, ncols - 1) * n;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < kDenseLdsJ; ++j) {
+                const int k = min(4 * j + q, nm1);
+                a0 = fma(areg[j], x0[k], a0);
+                a1 = fma(areg[j], x1[k], a1);
+            }
+            a0 = quad_sum(a0);
+            a1 = quad_sum(a1);
+            if (q == 0 && i < n) {
+                ds.Y[i][c0] = a0 - shift * x0[i];
+                if (c0 + 1 < ncols)
+                    ds.Y[i][c0 + 1] = a1 - shift * x1[i];
+            }
+        }
     }
     __syncthreads();
 }
@@ -270,6 +329,24 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     auto &Cj = sh.Cj;
     auto &red = sh.red;
     const int64_t n = P.n;
+    // term blocks: the caller's global memory, or LDS for a small dense
+    // operator on one workgroup (A itself then held in registers, areg)
+    double *bS = P.S, *bU0 = P.U0, *bU1 = P.U1, *bE = P.E;
+    double areg[KIND == kDenseLds ? kDenseLdsJ : 1];
+    if constexpr (KIND == kDenseLds) {
+        extern __shared__ double lds_dyn[];
+        const int i = (threadIdx.x >> 6) * 16 + ((threadIdx.x & 63) >> 2), q = threadIdx.x & 3;
+#pragma unroll
+        for (int j = 0; j < kDenseLdsJ; ++j) {
+            const int k = 4 * j + q;
+            areg[j] = (i < n && k < n) ? P.op.dense[(int64_t)i * n + k] : 0.0;
+        }
+        const int64_t cW = P.cS > P.cR ? P.cS : P.cR;
+        bS = lds_dyn;
+        bU0 = bS + P.cS * n;
+        bU1 = bU0 + cW * n;
+        bE = bU1 + cW * n;
+    }
     int64_t lo, hi;
     if constexpr (EMEM) {
         // an even chunk: row pairs never straddle two workgroups
@@ -286,7 +363,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     double Ereg[EMEM ? 1 : RPT][2 * R];
     auto Eref = [&](int64_t row, auto q, int c) -> double & {
         if constexpr (EMEM)
-            return P.E[(int64_t)c * n + row];
+            return bE[(int64_t)c * n + row];
         else
             return Ereg[decltype(q)::value][c];
     };
@@ -318,9 +395,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             load_cached_row(A, row, crow[decltype(q)::value]);
         });
     int lr_off = 0;   // low rank: column of W^T X holding the operand's first column
-    DenseShared *dsp = nullptr;
-    if constexpr (KIND == kDense) {
-        __shared__ DenseShared dense_lds;
+    using DS = std::conditional_t<KIND == kDenseLds, DenseLdsShared, DenseShared>;
+    DS *dsp = nullptr;
+    if constexpr (is_dense(KIND)) {
+        __shared__ DS dense_lds;
         dsp = &dense_lds;
     }
     // dense operator: products of this workgroup's rows for the coming term
@@ -328,6 +406,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                           __attribute__((always_inline)) {
         if constexpr (KIND == kDense)
             dense_products(A.dense, n, lo, hi, X, ncols, shift, *dsp);
+        else if constexpr (KIND == kDenseLds)
+            dense_products_lds(areg, n, X, ncols, shift, *dsp);
     };
     auto opr = [&](int64_t row, auto q, const auto *X, int col0, double shift,
                    auto &y) __attribute__((always_inline)) {
@@ -335,7 +415,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         constexpr int NC = std::extent<Y>::value;
         using TA = std::remove_extent_t<Y>;
         using TX = std::remove_cv_t<std::remove_pointer_t<decltype(X)>>;
-        if constexpr (KIND == kDense) {
+        if constexpr (is_dense(KIND)) {
             // products computed by dense_products for this term
 #pragma unroll
             for (int j = 0; j < NC; ++j)
@@ -421,15 +501,15 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             for (int i = 0; i < R; ++i) {
                 const double u = vv * P.gam[i][b];
                 const int64_t o = (int64_t)(b * R + i) * n + row;
-                P.U0[o] = u;
-                P.S[o] = u;
+                bU0[o] = u;
+                bS[o] = u;
                 su += fabs(u);
             }
         }
         nrm[0] = nmax(nrm[0], su);
     });
-    publish(P.U0, P.cS, 0);
-    publish(P.S, R, P.cS * A.rank);   // S_0: operand of the first recovery product
+    publish(bU0, P.cS, 0);
+    publish(bS, R, P.cS * A.rank);   // S_0: operand of the first recovery product
     nrm[1] = nrm[0];
     if (!exchange(nrm)) {
         finish(PHICOMB_EDEVICE, 0, 0, 0);
@@ -482,8 +562,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             }
             __syncthreads();
         }
-        const double *Uo = par ? P.U1 : P.U0;
-        double *Un = par ? P.U0 : P.U1;
+        const double *Uo = par ? bU1 : bU0;
+        double *Un = par ? bU0 : bU1;
         const float *Uo32 = par ? P.Uf1 : P.Uf0;
         float *Un32 = par ? P.Uf0 : P.Uf1;
         double mx[2] = {0.0, 0.0};
@@ -559,10 +639,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                             *(typename Vec2<TS>::type *)(Un_ + o) = uv;
                             u0 = (double)uv.x;
                             u1 = (double)uv.y;
-                            auto sv = ld_pair(P.S + (int64_t)c * n, (unsigned)i0);
+                            auto sv = ld_pair(bS + (int64_t)c * n, (unsigned)i0);
                             sv.x += u0;
                             sv.y += u1;
-                            *(typename Vec2<double>::type *)(P.S + o) = sv;
+                            *(typename Vec2<double>::type *)(bS + o) = sv;
                             su0 += fabs(u0);
                             su1 += fabs(u1);
                             ss0 += fabs(sv.x);
@@ -594,8 +674,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                         const TS us = (TS)u;
                         Un_[o] = us;
                         u = (double)us;
-                        const double sn = P.S[o] + u;
-                        P.S[o] = sn;
+                        const double sn = bS[o] + u;
+                        bS[o] = sn;
                         su += fabs(u);
                         ss += fabs(sn);
                     }
@@ -619,7 +699,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             publish(Un32, P.cS, 0);
         else
             publish(Un, P.cS, 0);
-        publish(P.S, R, P.cS * A.rank);
+        publish(bS, R, P.cS * A.rank);
         if (!exchange(mx)) {
             finish(PHICOMB_EDEVICE, k, 0, 0);
             return;
@@ -643,17 +723,17 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
     double nF = 0.0;
     {
         double mx[1] = {0.0};
-        dense_pass(P.S, R, 0.0);
+        dense_pass(bS, R, 0.0);
         lr_off = P.cS;
         for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
             double y[R];
-            opr(row, q, P.S, 0, 0.0, y);
+            opr(row, q, bS, 0, 0.0, y);
             const double v0 = P.V[row * P1];
             double f1[R], f2[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 f1[i] = y[i] * P.t[i] + P.w0[i] * v0;
-                f2[i] = (p >= 1) ? P.S[(int64_t)(p * R + i) * n + row] : 0.0;
+                f2[i] = (p >= 1) ? bS[(int64_t)(p * R + i) * n + row] : 0.0;
             }
             if (one_step) {
 #pragma unroll
@@ -663,13 +743,13 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                 double sf = 0.0;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    P.U0[(int64_t)i * n + row] = f1[i];
+                    bU0[(int64_t)i * n + row] = f1[i];
                     Eref(row, q, i) = f1[i];
                     sf += fabs(f1[i]);
                 }
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    P.U0[(int64_t)(R + i) * n + row] = f2[i];
+                    bU0[(int64_t)(R + i) * n + row] = f2[i];
                     Eref(row, q, R + i) = f2[i];
                     sf += fabs(f2[i]);
                 }
@@ -681,7 +761,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
             return;
         }
         lr_off = 0;
-        publish(P.U0, 2 * R, 0);
+        publish(bU0, 2 * R, 0);
         if (!exchange(mx)) {
             finish(PHICOMB_EDEVICE, terms_S, 0, 0);
             return;
@@ -710,8 +790,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                                  nref >= P.mix_lo && nE <= P.mix_hi));
             d1 = d2;
             const double rk = 1.0 / (double)kk;
-            const double *Fo = par ? P.U1 : P.U0;
-            double *Fn = par ? P.U0 : P.U1;
+            const double *Fo = par ? bU1 : bU0;
+            double *Fn = par ? bU0 : bU1;
             const float *Fo32 = par ? P.Uf1 : P.Uf0;
             float *Fn32 = par ? P.Uf0 : P.Uf1;
             double mx[2] = {0.0, 0.0};
@@ -756,10 +836,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                                 const int64_t o = (int64_t)c * n + i0;
                                 typename Vec2<TS>::type fv = {(TS)f0, (TS)f1};
                                 *(typename Vec2<TS>::type *)(Fn_ + o) = fv;
-                                auto ev = ld_pair(P.E + (int64_t)c * n, (unsigned)i0);
+                                auto ev = ld_pair(bE + (int64_t)c * n, (unsigned)i0);
                                 ev.x += f0;
                                 ev.y += f1;
-                                *(typename Vec2<double>::type *)(P.E + o) = ev;
+                                *(typename Vec2<double>::type *)(bE + o) = ev;
                                 sf0 += fabs(f0);
                                 sf1 += fabs(f1);
                                 se0 += fabs(ev.x);
@@ -831,7 +911,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
         for (int d = 1; d < kPMax1; ++d)
             cd[d] = cd[d - 1] * ((double)j * P.nu) / (double)d;
         const bool last = (j == P.s_int - 1);
-        double *Fx = par ? P.U1 : P.U0;   // overwrite the latest term: only E is needed
+        double *Fx = par ? bU1 : bU0;   // overwrite the latest term: only E is needed
         double mx[1] = {0.0};
         for_rows<RPT, EMEM, NT>(lo, hi, [&](int64_t row, auto q) {
             double f1[R], f2[R];
@@ -840,7 +920,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs &P, SolveShared &sh, 
                 f1[i] = Eref(row, q, i) * P.mu[i];
                 double acc = Eref(row, q, R + i) * P.mu[i];
                 for (int b = 1; b <= p; ++b)
-                    acc += P.S[(int64_t)(b * R + i) * n + row] * cd[p - b];
+                    acc += bS[(int64_t)(b * R + i) * n + row] * cd[p - b];
                 f2[i] = acc;
             }
             if (last) {
@@ -882,6 +962,19 @@ __global__ __launch_bounds__(NT) void solve_kernel(SolveArgs P) {
     __shared__ SolveShared sh;
     solve_body<KIND, R, RPT, EMEM, MIX, NT>(P, sh, gridDim.x, blockIdx.x,
                                             xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+// A small dense operator on one workgroup, A in registers and the term
+// blocks in LDS (dynamic shared memory of dense_lds_bytes).  The caller's blocks in global
+// memory are not used; V is read and W written as in the other variants.
+template <int R>
+__global__ __launch_bounds__(kNT) void solve_kernel_dense_lds(SolveArgs P) {
+    __shared__ SolveShared sh;
+    solve_body<kDenseLds, R, 1, true, false, kNT>(P, sh, 1u, 0u, 0);
+}
+
+__host__ __device__ constexpr size_t dense_lds_bytes(int64_t n, int64_t cS, int64_t cR) {
+    return sizeof(double) * (size_t)(n * (cS + 2 * (cS > cR ? cS : cR) + cR));
 }
 
 using KernelFn = void (*)(SolveArgs);
@@ -929,6 +1022,7 @@ KernelFn pick_stencil_wide(int r, bool mix);
 KernelFn pick_csr(int r, int rpt, bool emem, bool mix);
 KernelFn pick_csr_cached(int r, int rpt, bool mix);   // E in registers only
 KernelFn pick_dense(int r);                            // E in memory, FP64
+KernelFn pick_dense_lds(int r);                        // n <= kDenseLdsN, all in LDS, FP64
 
 // ---------------------------------------------------------------- host side
 // (implemented in solve.hip)
