@@ -26,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "phicomb_oracle.c")
+_ZSRC = os.path.join(_HERE, "phicomb_oracle_complex.c")   # Algorithms 1 and 3 over C
 _LIB = os.path.join(_HERE, "libphicomb_oracle.so")
 _lib = None
 
@@ -47,7 +48,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no FP contraction)."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11",
-               "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, _ZSRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -91,6 +92,13 @@ def _configure(lib):
     lib.orc_apply.restype = None
     lib.orc_binom.argtypes = [C.c_int, C.c_int]
     lib.orc_binom.restype = C.c_double
+    if hasattr(lib, "orz_solve"):   # builds of the real source alone lack them
+        lib.orz_params.argtypes = [P, C.c_double, C.c_int, P, C.c_double, C.c_double,
+                                   C.c_int, P]
+        lib.orz_params.restype = C.c_int
+        lib.orz_solve.argtypes = [P, C.c_int, C.c_int, P, P, P, C.c_int, P, C.c_double, P,
+                                  C.c_double, C.c_int, P, P]
+        lib.orz_solve.restype = C.c_int
     return lib
 
 
@@ -349,3 +357,75 @@ def series_block(op, p: int, r: int, t, beta, V: np.ndarray, tol: float, kcap: i
         G = G + T
         c1, c2 = c2, np.abs(T).sum(axis=1).max()
     return G, {"terms": j + 1}
+
+
+# ----------------------------------------------------------- complex data
+class _ZOp(C.Structure):
+    _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("pad", C.c_int32),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("dense", C.c_void_p)]
+
+
+class ZOperator:
+    """A complex operator for the complex oracle: a dense n x n array, or CSR
+    (rowptr, col, val) with complex values.  Keeps the arrays alive."""
+
+    def __init__(self, dense=None, csr=None):
+        s = _ZOp()
+        self.keep = []
+        if dense is not None:
+            A = np.ascontiguousarray(dense, dtype=np.complex128)
+            self.keep.append(A)
+            s.n, s.kind, s.dense = A.shape[0], 1, A.ctypes.data
+        else:
+            rp, ci, va = csr
+            rp = np.ascontiguousarray(rp, dtype=np.int32)
+            ci = np.ascontiguousarray(ci, dtype=np.int32)
+            va = np.ascontiguousarray(va, dtype=np.complex128)
+            self.keep += [rp, ci, va]
+            s.n, s.kind = rp.shape[0] - 1, 0
+            s.rowptr, s.col, s.val = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+        self.s = s
+        self.n = int(s.n)
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def zparams(op: ZOperator, tol: float, v: np.ndarray, m: int = 61,
+            brent_rel: float = BRENT_REL, brent_abs: float = BRENT_ABS,
+            brent_maxit: int = BRENT_MAXIT) -> dict:
+    """Algorithm 1 for a complex operator from a real start vector v; the
+    shift is searched on the real line as in the listing (real xi*)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = _Params()
+    st = _load().orz_params(op.ref, tol, m, _ptr(v), brent_rel, brent_abs, brent_maxit,
+                            C.byref(out))
+    if st != 0:
+        raise OracleError(st)
+    res = {f: getattr(out, f) for f, _ in _Params._fields_}
+    res["tol"] = tol
+    return res
+
+
+def zsolve(op: ZOperator, p: int, r: int, t, beta, V: np.ndarray, tol: float, shift,
+           s: float, form: str = "beta", alpha=None, kcap: int = KCAP):
+    """Algorithm 3 over C.  t [r], beta [r][p+1] (form "beta") or alpha [r]
+    (form "alpha"), V [n][p+1], shift complex.  Returns (W [n][r], stats)."""
+    n = op.n
+    t = np.ascontiguousarray(t, dtype=np.complex128)
+    Vc = np.ascontiguousarray(np.asarray(V, dtype=np.complex128).T)
+    assert Vc.shape == (p + 1, n)
+    b = np.ascontiguousarray(beta, dtype=np.complex128) if beta is not None else None
+    a = np.ascontiguousarray(alpha, dtype=np.complex128) if alpha is not None else None
+    xi = np.array([complex(shift)], dtype=np.complex128)
+    Wc = np.zeros((r, n), dtype=np.complex128)
+    stt = _Stats()
+    st = _load().orz_solve(op.ref, p, r, _ptr(t), _ptr(b) if b is not None else None,
+                           _ptr(a) if a is not None else None, 0 if form == "beta" else 1,
+                           _ptr(Vc), tol, _ptr(xi), s, kcap, _ptr(Wc), C.byref(stt))
+    if st != 0:
+        raise OracleError(st)
+    stats = {f: getattr(stt, f) for f, _ in _Stats._fields_ if f != "pad"}
+    return np.ascontiguousarray(Wc.T), stats

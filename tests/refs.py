@@ -102,6 +102,39 @@ def augmented_mp(A: np.ndarray, t_i: float, beta_i: np.ndarray, V: np.ndarray,
         return np.array([float(w[a]) for a in range(n)])
 
 
+def augmented_mp_c(A: np.ndarray, t_i: complex, beta_i: np.ndarray, V: np.ndarray,
+                   dps: int = 40) -> np.ndarray:
+    """Exact w_i over C from the augmented exponential (Theorem 1):
+    w_i = [I 0] exp([[t_i A, W_i], [0, J_p(0)]]) [beta_i0 v_0; e_p], with
+    W_i = [beta_ip v_p, ..., beta_i1 v_1]; complex A, t_i, beta_i, V."""
+    n, P1 = V.shape
+    p = P1 - 1
+    mc = lambda z: mpmath.mpc(complex(z).real, complex(z).imag)
+    with mpmath.workdps(dps):
+        M = mpmath.zeros(n + p, n + p)
+        for a in range(n):
+            for b in range(n):
+                M[a, b] = mc(t_i) * mc(A[a, b])
+        for c in range(p):
+            j = p - c
+            for a in range(n):
+                M[a, n + c] = mc(beta_i[j]) * mc(V[a, j])
+        for c in range(p - 1):
+            M[n + c, n + c + 1] = 1
+        E = mpmath.expm(M)
+        rhs = mpmath.zeros(n + p, 1)
+        for a in range(n):
+            rhs[a] = mc(beta_i[0]) * mc(V[a, 0])
+        if p > 0:
+            rhs[n + p - 1] = 1
+        w = E * rhs
+        return np.array([complex(w[a]) for a in range(n)])
+
+
+def exact_dense_mp_c(A, t, beta, V, dps=40):
+    return np.stack([augmented_mp_c(A, t[i], beta[i], V, dps) for i in range(len(t))], axis=1)
+
+
 def exact_dense_mp(A, t, beta, V, dps=40):
     return np.stack([augmented_mp(A, t[i], beta[i], V, dps) for i in range(len(t))], axis=1)
 

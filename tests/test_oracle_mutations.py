@@ -142,3 +142,62 @@ def test_planted_mistake_is_caught(orc, tmp_path, original_source, name, old, ne
     with orc.using_library(str(lib)):
         failed = _battery(orc)
     assert failed, f"planted mistake '{name}' passed every pin"
+
+
+# ------------------------------------------------------------- complex oracle
+ZSRC = os.path.join(os.path.dirname(SRC), "phicomb_oracle_complex.c")
+
+ZMUTATIONS = [
+    ("S-series step with Re t", "const zc ts = t[i] / ssd;", "const zc ts = creal(t[i]) / ssd;"),
+    ("undo factor with conj(xi)", "mu[i] = cexp(xi * t[i] / ssd);",
+     "mu[i] = cexp(conj(xi) * t[i] / ssd);"),
+    ("block norm of real parts", "s += cabs(X[(int64_t)q * n + i]);",
+     "s += fabs(creal(X[(int64_t)q * n + i]));"),
+    ("recovery of v_0 with conj(t)", "fc[q] = y[q] * t[i] + w0 * V[q];",
+     "fc[q] = y[q] * conj(t[i]) + w0 * V[q];"),
+    ("J step with conj(xi)", "js[bb * P1 + bb] = (-xi * t[i]) / ssd;",
+     "js[bb * P1 + bb] = (-conj(xi) * t[i]) / ssd;"),
+    ("Delta = conj(alpha)", "Dl[i] = (form == 1) ? alpha[i] : 1.0;",
+     "Dl[i] = (form == 1) ? conj(alpha[i]) : 1.0;"),
+    ("conjugated dense operand", "acc += row[j] * x[j];", "acc += conj(row[j]) * x[j];"),
+    ("s_int from |Re t|", "if (cabs(t[i]) > tmax)\n            tmax = cabs(t[i]);",
+     "if (fabs(creal(t[i])) > tmax)\n            tmax = fabs(creal(t[i]));"),
+    ("conjugated weight table", "const zc wgt = (form == 0) ? beta[i * P1 + zperm(bl, p)] : 1.0;",
+     "const zc wgt = (form == 0) ? conj(beta[i * P1 + zperm(bl, p)]) : 1.0;"),
+]
+
+
+def _zbattery(orc):
+    """Compact complex pins; returns the names of the failed ones."""
+    import test_oracle_complex as tz
+    failed = []
+    for name, fn, args in [
+        ("z-diag", tz.test_complex_diagonal_closed_form, (1, 10.0)),
+        ("z-dense", tz.test_complex_dense_against_augmented_exponential, (7, 5, 3, 1, 8.0)),
+        ("z-real", tz.test_complex_path_on_real_data_equals_real_oracle, ()),
+        ("z-imag", tz.test_complex_purely_imaginary_data, ()),
+    ]:
+        try:
+            fn(orc, *args)
+        except Exception:
+            failed.append(name)
+    return failed
+
+
+def test_unmutated_complex_battery_passes(orc):
+    assert _zbattery(orc) == []
+
+
+@pytest.mark.parametrize("name,old,new", ZMUTATIONS, ids=[m[0] for m in ZMUTATIONS])
+def test_planted_complex_mistake_is_caught(orc, tmp_path, name, old, new):
+    with open(ZSRC) as f:
+        zsrc = f.read()
+    assert zsrc.count(old) == 1, f"mutation anchor not unique/not found: {name}"
+    src = tmp_path / "zmutant.c"
+    src.write_text(zsrc.replace(old, new))
+    lib = tmp_path / "libzmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=gnu11", "-fPIC", "-shared",
+                           "-w", "-o", str(lib), SRC, str(src), "-lm"])
+    with orc.using_library(str(lib)):
+        failed = _zbattery(orc)
+    assert failed, f"planted mistake '{name}' passed every complex pin"

@@ -2,7 +2,7 @@
 (CPU only): the oracle and the quadruple-precision reference are compiled
 with -fsanitize=address,undefined (errors fatal) and exercised in a child
 process with the sanitizer runtime preloaded: Algorithms 1-3 on stencil,
-CSR, dense and low-rank operators, ragged sizes, p = 0 and p = 7, the single
+CSR, dense and low-rank operators (and over C on complex dense and CSR ones), ragged sizes, p = 0 and p = 7, the single
 block series, the integrator and the error paths (bad arguments, term cap,
 overflow guard).  Any out-of-bounds access, use after free or undefined
 operation aborts the child, and the test fails with its report."""
@@ -57,6 +57,26 @@ CHILD = textwrap.dedent(r"""
         pass
     pq = wl.small_problem(4, 2, 1, seed=3)
     refs.exact_dense_q(pq.op.A, pq.t, pq.beta, pq.V)
+    # the complex algorithms: dense and CSR, p = 0 and p = 5, error paths
+    rng = np.random.default_rng(4)
+    for n, p, r in ((7, 5, 3), (3, 0, 1)):
+        Az = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) - 3.0 * np.eye(n)
+        zop = oracle.ZOperator(dense=Az)
+        zp = oracle.zparams(zop, 2.0 ** -53, np.ones(n))
+        tz = np.exp(1j * np.arange(r)) * 4.0
+        Vz = rng.standard_normal((n, p + 1)) + 1j * rng.standard_normal((n, p + 1))
+        oracle.zsolve(zop, p, r, tz, np.ones((r, p + 1)), Vz, 1e-12, zp["shift"] + 1j, zp["s"])
+        oracle.zsolve(zop, p, r, tz, None, Vz, 1e-12, zp["shift"], zp["s"], form="alpha",
+                      alpha=np.ones(r) * 1j)
+    zc = oracle.ZOperator(csr=(np.arange(5), np.arange(4), np.full(4, 1e300 + 0j)))
+    try:
+        oracle.zparams(zc, 1e-8, np.ones(4))
+    except oracle.OracleError:
+        pass
+    try:
+        oracle.zsolve(zc, 1, 1, [np.nan], np.ones((1, 2)), np.ones((4, 2)), 1e-8, 0.0, 1.0)
+    except oracle.OracleError:
+        pass
     print("SANITIZED_OK")
 """)
 
@@ -77,6 +97,8 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
     lib = str(tmp_path / "liborc_asan.so")
     subprocess.check_call(["gcc"] + flags + ["-o", lib,
                                              os.path.join(ROOT, "oracle", "phicomb_oracle.c"),
+                                             os.path.join(ROOT, "oracle",
+                                                          "phicomb_oracle_complex.c"),
                                              "-lm"])
     # the quadruple-precision reference, sanitized too, where refs looks for it
     qlib = str(tmp_path / "libexact_q.so")
