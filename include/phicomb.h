@@ -358,6 +358,49 @@ int phicomb_exprk4s6(phicomb_op op, const phicomb_params_t *prm, const double g[
                      int nsteps, double tol, int precision, void *u, void *stream,
                      phicomb_exprk_stats_t *stats);
 
+/* ---------------------------------------------------------- complex data
+ * Sec. 1 poses the problem over C: A in C^{n x n}, V in C^{n x (p+1)}, complex
+ * t_i and weights; Algorithm 3 takes a shift xi in C; Algorithm 1's listing
+ * searches xi on the real line from a real start vector, so its xi* is real.
+ * Complex arrays are interleaved (re, im) doubles (the layout of C99
+ * double complex and of torch.complex128).  FP64 only. */
+typedef struct phicomb_zop_s *phicomb_zop;
+
+/* Complex CSR operator (host arrays, copied): rowptr [n+1], col [nnz],
+ * val [2 nnz] interleaved.  1 <= n, 2n <= PHICOMB_MAX_N.  The operator also
+ * keeps its real 2n x 2n representation [[Re A, -Im A], [Im A, Re A]] for
+ * Algorithm 1.  Errors: EINVAL (bad structure, non-finite value), ENOMEM,
+ * EDEVICE. */
+int phicomb_zop_create_csr(int64_t n, const int32_t *rowptr, const int32_t *col,
+                           const double *val, phicomb_zop *out);
+
+/* Complex dense operator, A [n][n] row-major interleaved (host, copied);
+ * n <= 16384. */
+int phicomb_zop_create_dense(int64_t n, const double *A, phicomb_zop *out);
+
+int phicomb_zop_destroy(phicomb_zop op);
+
+/* Algorithm 1 (Sec. 3) for a complex operator: the real parameter kernel on
+ * the operator's real representation from the start vector [v; 0], which
+ * gives the same powers' 2-norms, objective and (real) xi*, s as the complex
+ * listing.  v: host [n] real, or NULL for SplitMix64(seed, i) in [-1, 1). */
+int phicomb_zparams(phicomb_zop op, double tol, int m, const double *v, uint64_t seed,
+                    void *stream, phicomb_params_t *out);
+
+/* Algorithm 3 (Sec. 4) over C, beta-prescaled form:
+ *   w_i = sum_j beta_ij phi_j(t_i A) v_j,  i = 1..r.
+ *   prm    parameters of phicomb_zparams (s, and the shift unless given)
+ *   shift  host [2] complex shift xi, or NULL for prm->shift
+ *   t      host [r] complex;  beta host [r][p+1] complex
+ *   V      device [n][p+1] complex row-major;  W device [n][r] complex, written
+ *   stats  optional (s_int, term counts, kernel time; bytes_alg not set)
+ * One persistent launch, blocking on stream.  Errors: EINVAL (arguments,
+ * non-finite V found on the device), ENOCONV (a Taylor loop reached 150
+ * terms), EDEVICE (launch, barrier time-out, or a non-finite norm later). */
+int phicomb_zsolve(phicomb_zop op, const phicomb_params_t *prm, const double *shift, int p,
+                   int r, const double *t, const double *beta, const void *V, double tol,
+                   void *W, void *stream, phicomb_stats_t *stats);
+
 const char *phicomb_strerror(int status);
 
 #ifdef __cplusplus

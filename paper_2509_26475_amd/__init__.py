@@ -105,6 +105,11 @@ def _lib():
             "phicomb_exprk4s6": ([P, P, P, D, I32, D, I32, P, P, P], I32),
             "phicomb_solve_series": ([P, I32, I32, P, P, P, D, P, P, P], I32),
             "phicomb_op_apply": ([P, P, I32, D, P, P, P], I32),
+            "phicomb_zop_create_csr": ([I64, P, P, P, P], I32),
+            "phicomb_zop_create_dense": ([I64, P, P], I32),
+            "phicomb_zop_destroy": ([P], I32),
+            "phicomb_zparams": ([P, D, I32, P, C.c_uint64, P, P], I32),
+            "phicomb_zsolve": ([P, P, P, I32, I32, P, P, P, D, P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -388,6 +393,65 @@ def _check_device_tensor(x, shape, name):
         raise TypeError(f"{name} must be a float64 torch tensor on the GPU")
     if not x.is_contiguous() or x.dim() != 2 or (shape[1] is not None and x.shape[1] != shape[1]):
         raise ValueError(f"{name} must be contiguous [n][{shape[1]}], got {tuple(x.shape)}")
+
+
+# ---------------------------------------------------------------- complex data
+def phicomb_zop_create_csr(n: int, rowptr, col, val):
+    """Complex CSR operator; val complex [nnz] (host)."""
+    _require_gpu()
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    va = np.ascontiguousarray(val, dtype=np.complex128)
+    h = C.c_void_p()
+    _check(_lib().phicomb_zop_create_csr(int(n), _np_ptr(rp), _np_ptr(ci), _np_ptr(va),
+                                         C.byref(h)), "phicomb_zop_create_csr")
+    return h
+
+
+def phicomb_zop_create_dense(A):
+    """Complex dense operator from a complex [n][n] array (host)."""
+    _require_gpu()
+    a = np.ascontiguousarray(A, dtype=np.complex128)
+    h = C.c_void_p()
+    _check(_lib().phicomb_zop_create_dense(int(a.shape[0]), _np_ptr(a), C.byref(h)),
+           "phicomb_zop_create_dense")
+    return h
+
+
+def phicomb_zop_destroy(h) -> None:
+    _check(_lib().phicomb_zop_destroy(h), "phicomb_zop_destroy")
+
+
+def phicomb_zparams(h, tol: float, m: int = 61, v: Optional[np.ndarray] = None, seed: int = 1,
+                    stream=None) -> ParamsT:
+    out = ParamsT()
+    va = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+    st = _lib().phicomb_zparams(h, float(tol), int(m), _np_ptr(va) if va is not None else None,
+                                int(seed), _stream_ptr(stream), C.byref(out))
+    _check(st, "phicomb_zparams")
+    return out
+
+
+def phicomb_zsolve(h, prm: ParamsT, p: int, r: int, t, beta, V, tol: float, W, shift=None,
+                   stream=None) -> StatsT:
+    """V: torch complex128 cuda tensor [n][p+1]; W: torch complex128 [n][r];
+    t [r] and beta [r][p+1] complex (host); shift complex or None (prm.shift)."""
+    import torch
+    ta = np.ascontiguousarray(t, dtype=np.complex128)
+    ba = np.ascontiguousarray(beta, dtype=np.complex128)
+    for x, name, c in ((V, "V", p + 1), (W, "W", r)):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.complex128:
+            raise TypeError(f"{name} must be a complex128 torch tensor on the GPU")
+        if not x.is_contiguous() or x.dim() != 2 or x.shape[1] != c:
+            raise ValueError(f"{name} must be contiguous [n][{c}], got {tuple(x.shape)}")
+    xa = None if shift is None else np.array([complex(shift)], dtype=np.complex128)
+    stats = StatsT()
+    st = _lib().phicomb_zsolve(h, C.byref(prm), _np_ptr(xa) if xa is not None else None,
+                               int(p), int(r), _np_ptr(ta), _np_ptr(ba),
+                               C.c_void_p(V.data_ptr()), float(tol), C.c_void_p(W.data_ptr()),
+                               _stream_ptr(stream), C.byref(stats))
+    _check(st, "phicomb_zsolve")
+    return stats
 
 
 # ---------------------------------------------------------------- conveniences

@@ -18,8 +18,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # compile in parallel (the largest units first)
 SOURCES = ["batch_stencil.hip", "batch_csr.hip", "solve_stencil.hip", "solve_csr.hip",
            "solve_csr_cached.hip", "solve_lowrank.hip", "solve_dense.hip", "params.hip",
-           "series.hip", "apply.hip", "exprk.hip", "solve.hip", "batch.hip", "api.cpp",
-           "serve.cpp"]
+           "series.hip", "apply.hip", "exprk.hip", "solve.hip", "batch.hip", "zsolve.hip",
+           "api.cpp", "serve.cpp"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
