@@ -356,6 +356,46 @@ def bench_series(pc, wl, torch) -> dict:
     return out
 
 
+def bench_complex(pc, wl, torch) -> dict:
+    """Complex data (Sec. 1): A = (1 + 0.5i) L + diag(pot), L the 2-D 5-point
+    Laplacian on a 512 x 512 grid (CSR, n = 2^18), pot complex N(0, 50^2),
+    p = 2, r = 2, complex t, complex weights and V, tol 1e-12: Algorithm 1
+    on the real representation, Algorithm 3 in the complex kernel."""
+    import numpy as np
+    import scipy.sparse as sp
+    m = 512
+    n = m * m
+    rng = np.random.default_rng(7)
+    h2 = (m + 1.0) ** 2
+    T = sp.diags([np.full(m - 1, h2), np.full(m, -2.0 * h2), np.full(m - 1, h2)], [-1, 0, 1])
+    L = sp.kron(sp.identity(m), T) + sp.kron(T, sp.identity(m))
+    pot = 50.0 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    A = ((1.0 + 0.5j) * L + sp.diags(pot)).tocsr()
+    A.sort_indices()
+    p, r, tol = 2, 2, 1e-12
+    t = 2e-4 * np.array([1.0, 0.5]) * np.exp(0.3j)
+    beta = rng.standard_normal((r, p + 1)) + 1j * rng.standard_normal((r, p + 1))
+    V = torch.from_numpy(rng.standard_normal((n, p + 1)) + 1j * rng.standard_normal((n, p + 1))).cuda()
+    W = torch.empty((n, r), dtype=torch.complex128, device="cuda")
+    h = pc.phicomb_zop_create_csr(n, A.indptr, A.indices, A.data)
+    try:
+        t0 = time.perf_counter()
+        prm = pc.phicomb_zparams(h, tol, 61, None, 1)
+        torch.cuda.synchronize()
+        t_par = time.perf_counter() - t0
+        st = None
+        for _ in range(2):
+            st = pc.phicomb_zsolve(h, prm, p, r, t, beta, V, tol, W)
+        terms = st.terms_S + st.terms_rec
+        return {"workload": "complex (1+0.5i) 2-D Laplacian 512^2 + complex potential, CSR, "
+                            "p=2, r=2, complex t, tol 1e-12",
+                "params_ms": 1e3 * t_par, "solve_kernel_ms": st.ms, "s_int": st.s_int,
+                "terms_S": st.terms_S, "terms_rec": st.terms_rec,
+                "us_per_term": 1e3 * st.ms / max(1, terms)}
+    finally:
+        pc.phicomb_zop_destroy(h)
+
+
 def bench_spmm(pc, wl, torch) -> dict:
     """The block product Y = (A - xi I) X alone on the 128^3 Laplacian
     (n = 2^21) as a 7-point stencil and as CSR, c = 4, 6, 12 columns:
@@ -629,7 +669,7 @@ def main(argv=None) -> int:
                          "block product, served stream)")
     ap.add_argument("--extras", default=None,
                     help="comma-separated subset of the extra sections to run (mixed_tol1e-6, "
-                         "convdiff512, batched, exp2, exp3, exp4, series, spmm, served); "
+                         "convdiff512, batched, exp2, exp3, exp4, series, spmm, complex, served); "
                          "default all")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -715,6 +755,7 @@ def main(argv=None) -> int:
         ("exp4", "fourth experiment", lambda: bench_exp4(pc, wl, torch)),
         ("series", "single block series", lambda: bench_series(pc, wl, torch)),
         ("spmm", "block product", lambda: bench_spmm(pc, wl, torch)),
+        ("complex", "complex data", lambda: bench_complex(pc, wl, torch)),
     ]
     if args.serve_seconds > 0:
         sections.append(("served", "served stream",
