@@ -280,9 +280,10 @@ int phicomb_batch_info(phicomb_batch b, int *groups, int *workgroups, double *pr
  * after another.  Every successful run refits it from the device clocks of
  * its instances (the per-round constants by least squares over instances of
  * 4 or more rounds, then the exchange constants from the remainders of
- * instances of few rounds, where the exchange dominates) and
- * rebuilds the schedule when the refit predicts a makespan 10 % below the
- * measured one.  get (optional, 5 doubles)
+ * instances of few rounds, where the exchange dominates; every instance
+ * weighted by its term count), rebuilds the schedule when the refit
+ * predicts a makespan 10 % below the measured one (at most 3 times), and
+ * returns to the fastest plan measured when a rebuilt one ran slower.  get (optional, 5 doubles)
  * receives the current model; set (optional, 5 non-negative doubles, e.g. a
  * model saved from an earlier plan by an autotuner) replaces it and rebuilds
  * the schedule (EINVAL for a negative or non-finite value). */

@@ -79,10 +79,10 @@ struct ItemCost {
 // instances), and the autotuner keeps the fitted model on disk.
 struct Model {
     double e1 = 1.5;     // single-workgroup exchange (us)
-    double e2 = 4.0;     // grid exchange (us)
-    double g2 = 0.03;    // growth of the grid exchange per workgroup (us)
-    double l0 = 0.5;     // one round of rows (us)
-    double l1 = 1.2;     // one round of rows, per column (us)
+    double e2 = 2.1;     // grid exchange (us)
+    double g2 = 0.021;   // growth of the grid exchange per workgroup (us)
+    double l0 = 0.05;    // one round of rows (us)
+    double l1 = 1.27;    // one round of rows, per column (us)
 };
 static thread_local Model t_model;
 
@@ -95,6 +95,8 @@ static double term_us(const ItemCost &c, int G) {
     return ex + rounds(c, G) * (m.l0 + m.l1 * c.cols);
 }
 static double cost_us(const ItemCost &c, int G) { return c.terms * term_us(c, G); }
+
+constexpr int kExplore = 3;   // refit plans a batch tries before keeping its best
 
 struct Schedule {
     std::vector<int> gsize;                 // per group
@@ -208,6 +210,9 @@ struct phicomb_batch_s {
     int precision = 0;
     bool mix = false;
     int runs = 0;                 // runs whose clocks refit the model
+    int explored = 0;             // plans tried after a refit
+    double best_ms = 0.0;         // fastest measured launch and its schedule
+    Schedule best_sched;
     double last_measured_ms = 0.0, last_predicted_ms = 0.0, refit_predicted_ms = 0.0;
     int cap = 0;                  // workgroups the launch may use
     std::vector<phicomb_op> ops;
@@ -269,9 +274,9 @@ size_t table_ints(int count, int cap) { return (size_t)2 * count + cap + 3 * (si
 
 // Schedule with the plan's model, then the launch tables (the layout of an
 // instance depends on the size of its group).  Drops the captured graph.
-int build_plan(phicomb_batch b) {
+int build_plan(phicomb_batch b, const Schedule *use = nullptr) {
     t_model = b->model;
-    b->sched = make_schedule(b->cost, b->cap);
+    b->sched = use ? *use : make_schedule(b->cost, b->cap);
     b->wgs = b->sched.wgs;
     b->ng = (int)b->sched.gsize.size();
     const int count = b->count, ng = b->ng;
@@ -310,24 +315,27 @@ int build_plan(phicomb_batch b) {
 // columns, measured microseconds per term), in two stages so that every
 // constant stays physical: the per-round constants (l0, l1) by least squares
 // over the samples whose rounds dominate (4 or more rounds), then the
-// exchange constants from what remains: e1 the median remainder of the
+// exchange constants from what remains: e1 the mean remainder of the
 // single-workgroup samples of at most 4 rounds, (e2, g2) a least-squares
 // line in G through the remainders of the grid samples of at most 2 rounds
-// (where the exchange is a large part of a term).  Constants without samples keep their
-// values; all are clamped to small positive floors.
+// (where the exchange is a large part of a term).  Constants without samples
+// keep their values; all are clamped to small positive floors.  The defaults
+// are such a fit to the device clocks of the 256-instance benchmark batch.
 struct Sample {
-    double G, rounds, cols, us;
+    double G, rounds, cols, us, terms;
 };
 
+// Weighted least squares for y ~ a x1 + b x2 (weights w).
 static bool lsq2(const std::vector<double> &x1, const std::vector<double> &x2,
-                 const std::vector<double> &y, double &a, double &b) {
+                 const std::vector<double> &y, const std::vector<double> &w, double &a,
+                 double &b) {
     double s11 = 0, s12 = 0, s22 = 0, s1y = 0, s2y = 0;
     for (size_t k = 0; k < y.size(); ++k) {
-        s11 += x1[k] * x1[k];
-        s12 += x1[k] * x2[k];
-        s22 += x2[k] * x2[k];
-        s1y += x1[k] * y[k];
-        s2y += x2[k] * y[k];
+        s11 += w[k] * x1[k] * x1[k];
+        s12 += w[k] * x1[k] * x2[k];
+        s22 += w[k] * x2[k] * x2[k];
+        s1y += w[k] * x1[k] * y[k];
+        s2y += w[k] * x2[k] * y[k];
     }
     const double det = s11 * s22 - s12 * s12;
     if (y.size() < 3 || !(std::fabs(det) > 1e-12 * (s11 * s22 + 1e-300)))
@@ -337,48 +345,47 @@ static bool lsq2(const std::vector<double> &x1, const std::vector<double> &x2,
     return std::isfinite(a) && std::isfinite(b);
 }
 
-static double median(std::vector<double> v) {
-    const size_t h = v.size() / 2;
-    std::nth_element(v.begin(), v.begin() + h, v.end());
-    return v[h];
-}
-
+// Every sample is weighted by its term count: the fit then matches the
+// instances that hold the launch's time (a few long chains), not the many
+// short ones whose per-term time is dominated by their few S-series terms.
 bool fit_model(const std::vector<Sample> &smp, Model &m) {
     Model out = m;
     {
-        std::vector<double> x1, x2, y;
+        std::vector<double> x1, x2, y, w;
         for (const Sample &s : smp)
             if (s.rounds >= 4.0) {
                 x1.push_back(s.rounds);
                 x2.push_back(s.rounds * s.cols);
                 y.push_back(s.us);
+                w.push_back(s.terms);
             }
         double a, b;
-        if (lsq2(x1, x2, y, a, b)) {
+        if (lsq2(x1, x2, y, w, a, b)) {
             out.l0 = std::max(a, 0.05);
             out.l1 = std::max(b, 0.05);
         }
     }
-    std::vector<double> r1, r2, g2;
+    double r1 = 0.0, w1 = 0.0;
+    std::vector<double> r2, g2, w2;
     for (const Sample &s : smp) {
         const double rest = s.us - s.rounds * (out.l0 + out.l1 * s.cols);
-        if (s.G == 1.0 && s.rounds <= 4.0)
-            r1.push_back(rest);
-        else if (s.G > 1.0 && s.rounds <= 2.0) {
+        if (s.G == 1.0 && s.rounds <= 4.0) {
+            r1 += s.terms * rest;
+            w1 += s.terms;
+        } else if (s.G > 1.0 && s.rounds <= 2.0) {
             r2.push_back(rest);
             g2.push_back(s.G);
+            w2.push_back(s.terms);
         }
     }
-    if (!r1.empty())
-        out.e1 = std::max(median(r1), 0.5);
+    if (w1 > 0.0)
+        out.e1 = std::max(r1 / w1, 0.5);
     if (!r2.empty()) {
         std::vector<double> ones(r2.size(), 1.0);
         double a, b;
-        if (lsq2(ones, g2, r2, a, b)) {
+        if (lsq2(ones, g2, r2, w2, a, b)) {
             out.e2 = std::max(a, 0.5);
             out.g2 = std::max(b, 0.0);
-        } else {
-            out.e2 = std::max(median(r2), 0.5);
         }
     }
     m = out;
@@ -416,7 +423,7 @@ void tune(phicomb_batch b, double measured_ms) {
         if (!(us > 0.0))
             continue;
         const int G = b->sched.gsize[group_of[it]];
-        smp.push_back({(double)G, rounds(b->cost[it], G), b->cost[it].cols, us / terms});
+        smp.push_back({(double)G, rounds(b->cost[it], G), b->cost[it].cols, us / terms, terms});
     }
     b->last_measured_ms = measured_ms;
     b->last_predicted_ms = predicted_ms(b);   // this run's plan, term counts now measured
@@ -424,10 +431,21 @@ void tune(phicomb_batch b, double measured_ms) {
     if (fit_model(smp, m))
         b->model = m;
     b->refit_predicted_ms = predicted_ms(b);
+    // keep the fastest plan measured so far; try a new one while the refit
+    // predicts 10 % less than this run (at most kExplore times), and go back
+    // to the best plan when a tried one measured slower
+    if (!(b->best_ms > 0.0) || measured_ms < b->best_ms) {
+        b->best_ms = measured_ms;
+        b->best_sched = b->sched;
+    }
     t_model = b->model;
     const Schedule trial = make_schedule(b->cost, b->cap);
-    if (trial.makespan * 1e-3 < 0.9 * measured_ms)
-        build_plan(b);
+    if (b->explored < kExplore && trial.makespan * 1e-3 < 0.9 * measured_ms) {
+        b->explored += 1;
+        build_plan(b, &trial);
+    } else if (measured_ms > 1.02 * b->best_ms) {
+        build_plan(b, &b->best_sched);
+    }
 }
 
 }  // namespace
