@@ -395,8 +395,9 @@ int phicomb_zparams(phicomb_zop op, double tol, int m, const double *v, uint64_t
  *   t      host [r] complex;  beta host [r][p+1] complex
  *   V      device [n][p+1] complex row-major;  W device [n][r] complex, written
  *   stats  optional (s_int, term counts, kernel time; bytes_alg not set)
- * One persistent launch, blocking on stream.  Errors: EINVAL (arguments,
- * non-finite V found on the device), ENOCONV (a Taylor loop reached 150
+ * One persistent launch, blocking on stream; the operator's device must be
+ * the current one.  Errors: EINVAL (arguments, another device, non-finite V
+ * found on the device), ENOCONV (a Taylor loop reached 150
  * terms), EDEVICE (launch, barrier time-out, or a non-finite norm later). */
 int phicomb_zsolve(phicomb_zop op, const phicomb_params_t *prm, const double *shift, int p,
                    int r, const double *t, const double *beta, const void *V, double tol,

@@ -668,8 +668,11 @@ int phicomb_zsolve(phicomb_zop op, const phicomb_params_t *prm, const double *sh
         }
     }
     std::lock_guard<std::mutex> g(op->mu);
-    if (hipSetDevice(op->device) != hipSuccess)
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
         return PHICOMB_EDEVICE;
+    if (cur != op->device)
+        return PHICOMB_EINVAL;   // the operator lives on another device
     const size_t blocks = 16 * (size_t)n * (size_t)(4 * cS + 3 * cR);
     const size_t o_tab = (blocks + 255) / 256 * 256;
     const size_t o_bar = o_tab + (sizeof(ZTables) + 255) / 256 * 256;
