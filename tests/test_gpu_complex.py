@@ -108,6 +108,9 @@ CASES = [
     ("csr75", lambda: _csr_case(75, 2, 4, 4, 1e-3)),               # 5625 rows: 11 workgroups
     ("csr60-imag-t", lambda: _csr_case(60, 2, 2, 5, 4e-3, coef=1.0, imag_t=True)),
     ("csr16-p0", lambda: _csr_case(16, 0, 1, 6, 5e-3)),
+    ("dense12-p7-r4", lambda: _dense_case(12, 7, 4, 8, 3.0)),         # largest p and r
+    ("csr400", lambda: _csr_case(400, 1, 1, 7, 1.2e-4)),              # 160 000 rows: 256 workgroups
+    ("dense1", lambda: _dense_case(1, 2, 2, 9, 2.0)),
 ]
 
 
