@@ -111,6 +111,33 @@ __device__ __forceinline__ double splitmix_unit(uint64_t seed, int64_t i) {
     return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// One lane's share of a dense row times x: sum of A[row][c] x[c] over
+// c = lane, lane + 64, ... in ascending c, one fused multiply-add each.  The
+// loads of kRowSteps of those terms are issued together (clamped into the
+// row, terms past it skipped), so a row costs n / (64 kRowSteps) memory
+// latencies rather than n / 64.
+constexpr int kRowSteps = 8;
+__device__ __forceinline__ double dense_row_dot(const double *__restrict__ arow,
+                                                const double *__restrict__ x, int64_t n,
+                                                int lane) {
+    double sum = 0.0;
+    for (int64_t b = 0; b < n; b += 64 * kRowSteps) {
+        double av[kRowSteps], xv[kRowSteps];
+#pragma unroll
+        for (int u = 0; u < kRowSteps; ++u) {
+            const int64_t c = b + 64 * u + lane;
+            const int64_t cc = c < n ? c : n - 1;
+            av[u] = arow[cc];
+            xv[u] = x[cc];
+        }
+#pragma unroll
+        for (int u = 0; u < kRowSteps; ++u)
+            if (b + 64 * u + lane < n)
+                sum = __builtin_fma(av[u], xv[u], sum);
+    }
+    return sum;
+}
+
 template <int KIND, int NT>
 __device__ __forceinline__ void params_body(const ParamsArgs &P) {
     __shared__ double wsc[NT / 64], wsq[NT / 64];
@@ -276,10 +303,7 @@ __device__ __forceinline__ void params_body(const ParamsArgs &P) {
         } else if constexpr (KIND == kDense) {
             // dense rows: one wave per row, lanes across the row, wave sum
             for (int64_t row = lo + (tid >> 6); row < hi; row += NT / 64) {
-                const double *arow = A.dense + row * n;
-                double sum = 0.0;
-                for (int64_t c = tid & 63; c < n; c += 64)
-                    sum += arow[c] * x[c];
+                double sum = dense_row_dot(A.dense + row * n, x, n, tid & 63);
                 sum = wave_sum(sum);
                 if ((tid & 63) == 0) {
                     const double val = (k == 1) ? sum / nv : sum;   // A (v/||v||)
@@ -373,10 +397,7 @@ __device__ __forceinline__ void params_body(const ParamsArgs &P) {
                 y[row] = lr_row(row) / s0;
         } else if constexpr (KIND == kDense) {
             for (int64_t row = lo + (tid >> 6); row < hi; row += NT / 64) {
-                const double *arow = A.dense + row * n;
-                double sum = 0.0;
-                for (int64_t c = tid & 63; c < n; c += 64)
-                    sum += arow[c] * x[c];
+                double sum = dense_row_dot(A.dense + row * n, x, n, tid & 63);
                 sum = wave_sum(sum);
                 if ((tid & 63) == 0)
                     y[row] = sum / s0;

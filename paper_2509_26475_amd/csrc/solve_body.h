@@ -129,6 +129,7 @@ constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predec
 constexpr int kDenseRows = 128;   // rows per workgroup at most
 constexpr int kDenseCols = 32;    // columns per product at most ((p+1) r)
 constexpr int kSolveWaves = kNT / 64;
+constexpr int kDenseSteps = 8;   // MFMA steps (of 4 k) whose loads are in flight together
 
 struct DenseShared {
     double Y[kDenseRows][kDenseCols + 1];   // products of the workgroup's rows
@@ -173,13 +174,26 @@ __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, in
         const double *xcol = X + (int64_t)(cok ? col : 0) * n;
         const int64_t kb = ks * kchunk, ke = std::min<int64_t>(n, kb + kchunk);
         mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        // unrolled so that the loads of several steps are in flight together
-#pragma unroll 8
-        for (int64_t k = kb + (lane >> 4); k - (lane >> 4) < ke; k += 4) {
-            const bool kok = k < ke;
-            const double a = (rok && kok) ? arow[k] : 0.0;
-            const double b = (cok && kok) ? xcol[k] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        // kDenseSteps steps a round: all their loads are issued before the
+        // first of their MFMAs, so a round costs one memory latency, not one
+        // per step.  Every load is in bounds (k clamped into the slice, whose
+        // last element exists) and a step past the slice multiplies zeros,
+        // so the accumulation is the plain ascending sequence of steps.
+        const int kq = lane >> 4;
+        for (int64_t kk = kb; kk < ke; kk += 4 * kDenseSteps) {
+            double a[kDenseSteps], b[kDenseSteps];
+#pragma unroll
+            for (int u = 0; u < kDenseSteps; ++u) {
+                const int64_t k = kk + 4 * u + kq;
+                const bool kok = k < ke;
+                const int64_t kc = kok ? k : ke - 1;
+                const double av = arow[kc], bv = xcol[kc];
+                a[u] = (rok && kok) ? av : 0.0;
+                b[u] = (cok && kok) ? bv : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kDenseSteps; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v)
