@@ -76,7 +76,7 @@ def test_apply_rejects_low_rank_and_bad_shapes():
     ((64, 64, 1), 2, -7.0),
     ((130, 3, 2), 3, 1.0),     # a grid line longer than a wave of pairs
 ])
-@pytest.mark.parametrize("ncols", [1, 5, 16])
+@pytest.mark.parametrize("ncols", [1, 5, 13, 16])
 def test_apply_stencil_row_pairs(grid, dim, sd, ncols):
     """Stencils with an even grid line take the row-pair kernel (x-neighbours
     across lanes, first and last lane of a wave loading their own); random
