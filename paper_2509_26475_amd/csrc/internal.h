@@ -723,7 +723,7 @@ int solve_run(phicomb_op op, const phicomb_params_t *prm, int p, int r, const do
               hipStream_t stream, phicomb_stats_t *stats, void *ws, size_t ws_bytes,
               double *pinned, int cu_floor = 0, hipEvent_t *events = nullptr);
 // Workgroups a solve on op asks the slot ledger for (want: one per CU up to
-// one per 512 rows, dense operators one per 32 rows) and the fewest it can
+// one per 512 rows, dense operators one per 16 rows) and the fewest it can
 // run with (floor: dense operators need one per kDenseRows rows).
 void solve_grid_request(phicomb_op op, int *want, int *floor_g);
 // rank > 0: a low-rank operator of that rank (adds the W^T X exchange area)

@@ -105,9 +105,10 @@ static double algorithmic_bytes(const DevOp &op, int64_t nnz, int64_t n, int p, 
 constexpr size_t kFrameOk = 64;
 
 // Dense operators: at most kDenseRows rows per workgroup (one workgroup up to
-// n = kDenseRows), else 32 rows per workgroup so that the k range of every
-// row tile is split over the waves; FP64 only.
-static int64_t dense_grid(int64_t n) { return n <= kDenseRows ? 1 : (n + 31) / 32; }
+// n = kDenseRows), else one 16-row tile per workgroup, so that the k range
+// of the tile is split over all eight waves and as many CUs as the grid
+// allows read A; FP64 only.
+static int64_t dense_grid(int64_t n) { return n <= kDenseRows ? 1 : (n + 15) / 16; }
 
 void solve_grid_request(phicomb_op op, int *want, int *floor_g) {
     const int64_t n = op->dev.n;

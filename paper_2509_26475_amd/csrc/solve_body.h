@@ -129,7 +129,7 @@ constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predec
 constexpr int kDenseRows = 128;   // rows per workgroup at most
 constexpr int kDenseCols = 32;    // columns per product at most ((p+1) r)
 constexpr int kSolveWaves = kNT / 64;
-constexpr int kDenseSteps = 8;   // MFMA steps (of 4 k) whose loads are in flight together
+constexpr int kDenseSteps = 16;  // MFMA steps (of 4 k) whose loads are in flight together
 
 struct DenseShared {
     double Y[kDenseRows][kDenseCols + 1];   // products of the workgroup's rows
