@@ -205,10 +205,12 @@ def test_small_dense_nonnormal():
 
 # Dense operators of at most 112 rows run on one workgroup with A and the
 # term blocks in LDS when they fit (p = 7, r = 4 at n = 112 does not and takes
-# the global-memory kernel, as do n = 113 and 128); ragged 16-row tiles at
-# n = 1, 17, 63, 99 and 112.
+# the global-memory kernel, as do n = 113 and 128 on one workgroup); ragged
+# 16-row tiles at n = 1, 17, 63, 99 and 112; past 128 rows one 16-row tile a
+# workgroup, the last one ragged (n = 129: a single row; n = 257).
 @pytest.mark.parametrize("n,p,r", [(1, 2, 1), (17, 1, 2), (63, 6, 1), (99, 6, 1), (99, 3, 4),
-                                   (112, 4, 3), (112, 7, 4), (113, 2, 2), (128, 6, 1)])
+                                   (112, 4, 3), (112, 7, 4), (113, 2, 2), (128, 6, 1),
+                                   (129, 2, 1), (257, 3, 2)])
 def test_dense_lds_sizes(n, p, r):
     pr = wl.small_problem(n, p, r, 11 + n, t_scale=3.0, spread=8.0)
     _compare(pr, label="dense")
