@@ -129,7 +129,10 @@ constexpr double kMixSafety = 8.0;   // allowed growth of a term over its predec
 constexpr int kDenseRows = 128;   // rows per workgroup at most
 constexpr int kDenseCols = 32;    // columns per product at most ((p+1) r)
 constexpr int kSolveWaves = kNT / 64;
-constexpr int kDenseSteps = 16;  // MFMA steps (of 4 k) whose loads are in flight together
+constexpr int kDenseBlocks = 4;   // blocks of 16 k whose loads are in flight together
+constexpr int kDenseTail = 8;     // steps of 4 k a round in the rest of a slice
+// two doubles at 8-byte alignment (a row of A starts at 8 n bytes)
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
 
 struct DenseShared {
     double Y[kDenseRows][kDenseCols + 1];   // products of the workgroup's rows
@@ -174,16 +177,43 @@ __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, in
         const double *xcol = X + (int64_t)(cok ? col : 0) * n;
         const int64_t kb = ks * kchunk, ke = std::min<int64_t>(n, kb + kchunk);
         mfma_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        // kDenseSteps steps a round: all their loads are issued before the
-        // first of their MFMAs, so a round costs one memory latency, not one
-        // per step.  Every load is in bounds (k clamped into the slice, whose
-        // last element exists) and a step past the slice multiplies zeros,
-        // so the accumulation is the plain ascending sequence of steps.
         const int kq = lane >> 4;
-        for (int64_t kk = kb; kk < ke; kk += 4 * kDenseSteps) {
-            double a[kDenseSteps], b[kDenseSteps];
+        // Whole blocks of 16 k, kDenseBlocks of them a round: a lane loads
+        // four consecutive k of its row of A and of its column of X (two
+        // 16-byte loads each, k0 = 16 j + 4 kq within the block), and MFMA
+        // step u of the block takes the u-th of them, so every k of the block
+        // is used once; all loads of a round are issued before its MFMAs.
+        // Rows and columns outside the operands read row lo or column 0 and
+        // contribute zeros.
+        int64_t kk = kb;
+        for (; kk + 16 * kDenseBlocks <= ke; kk += 16 * kDenseBlocks) {
+            dbl2u a[kDenseBlocks][2], b[kDenseBlocks][2];
 #pragma unroll
-            for (int u = 0; u < kDenseSteps; ++u) {
+            for (int j = 0; j < kDenseBlocks; ++j) {
+                const int64_t k0 = kk + 16 * j + 4 * kq;
+                a[j][0] = *(const dbl2u *)(arow + k0);
+                a[j][1] = *(const dbl2u *)(arow + k0 + 2);
+                b[j][0] = *(const dbl2u *)(xcol + k0);
+                b[j][1] = *(const dbl2u *)(xcol + k0 + 2);
+            }
+#pragma unroll
+            for (int j = 0; j < kDenseBlocks; ++j) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double av = (u < 2) ? a[j][0][u] : a[j][1][u - 2];
+                    const double bv = (u < 2) ? b[j][0][u] : b[j][1][u - 2];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rok ? av : 0.0, cok ? bv : 0.0,
+                                                               acc, 0, 0, 0);
+                }
+            }
+        }
+        // the rest of the slice (under 16 kDenseBlocks values of k): steps of
+        // four k in ascending order, k clamped into the slice (whose last
+        // element exists) and steps past it multiplying zeros
+        for (; kk < ke; kk += 4 * kDenseTail) {
+            double a[kDenseTail], b[kDenseTail];
+#pragma unroll
+            for (int u = 0; u < kDenseTail; ++u) {
                 const int64_t k = kk + 4 * u + kq;
                 const bool kok = k < ke;
                 const int64_t kc = kok ? k : ke - 1;
@@ -192,7 +222,7 @@ __device__ __forceinline__ void dense_products(const double *__restrict__ Ad, in
                 b[u] = (cok && kok) ? bv : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < kDenseSteps; ++u)
+            for (int u = 0; u < kDenseTail; ++u)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
         }
 #pragma unroll
