@@ -111,17 +111,35 @@ __device__ __forceinline__ double splitmix_unit(uint64_t seed, int64_t i) {
     return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// One lane's share of a dense row times x: sum of A[row][c] x[c] over
-// c = lane, lane + 64, ... in ascending c, one fused multiply-add each.  The
-// loads of kRowSteps of those terms are issued together (clamped into the
-// row, terms past it skipped), so a row costs n / (64 kRowSteps) memory
-// latencies rather than n / 64.
+// One lane's share of a dense row times x, one fused multiply-add a term.
+// Whole blocks of 128 kRowPairs entries first: lane l takes the pairs
+// (c, c + 1), c = 2 l + 128 u, each with one 16-byte load of A and of x, all
+// of a block's loads issued before its multiply-adds; then the rest of the
+// row (under 128 kRowPairs entries) in steps of 64 entries, c = lane + 64 u,
+// kRowSteps loads at a time (clamped into the row, entries past it skipped).
+constexpr int kRowPairs = 4;
 constexpr int kRowSteps = 8;
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
 __device__ __forceinline__ double dense_row_dot(const double *__restrict__ arow,
                                                 const double *__restrict__ x, int64_t n,
                                                 int lane) {
     double sum = 0.0;
-    for (int64_t b = 0; b < n; b += 64 * kRowSteps) {
+    int64_t b = 0;
+    for (; b + 128 * kRowPairs <= n; b += 128 * kRowPairs) {
+        dbl2u av[kRowPairs], xv[kRowPairs];
+#pragma unroll
+        for (int u = 0; u < kRowPairs; ++u) {
+            const int64_t c = b + 128 * u + 2 * lane;
+            av[u] = *(const dbl2u *)(arow + c);
+            xv[u] = *(const dbl2u *)(x + c);
+        }
+#pragma unroll
+        for (int u = 0; u < kRowPairs; ++u) {
+            sum = __builtin_fma(av[u].x, xv[u].x, sum);
+            sum = __builtin_fma(av[u].y, xv[u].y, sum);
+        }
+    }
+    for (; b < n; b += 64 * kRowSteps) {
         double av[kRowSteps], xv[kRowSteps];
 #pragma unroll
         for (int u = 0; u < kRowSteps; ++u) {
